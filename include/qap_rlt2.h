@@ -1,0 +1,185 @@
+/*
+ * qap_rlt2 -- level-2 RLT dual-ascent lower bound for the Quadratic
+ * Assignment Problem on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Goncalves, Pessoa, Drummond, Bentes, Farias, "Solving the Quadratic
+ * Assignment Problem on heterogeneous environment (CPUs and GPUs) with the
+ * application of Level 2 Reformulation and Linearization Technique",
+ * arXiv 1510.02065.  Problem statement: Section 2, equations (1)-(4).  Dual
+ * state and reduced-cost matrices B, C, D: Section 3.  Dual ascent:
+ * Section 4, Algorithm 1; cost concentration Section 4.1, spreading
+ * Section 4.2, complementary transfer Section 4.3.
+ *
+ * Conventions for every call
+ * --------------------------
+ *  - Every function returns a qap_status; nothing throws or aborts across the
+ *    ABI.  On a non-OK status qap_last_error() returns a thread-local message.
+ *  - Matrices are row-major, 0-based.  F[i*N+k] is the flow from facility i
+ *    to facility k; D[j*N+n] the distance from location j to location n.
+ *  - Inputs are copied; the caller keeps ownership of every buffer it passes.
+ *  - Handles are not thread-safe: use one handle from one thread at a time.
+ *  - Sizes: 3 <= N <= QAP_RLT2_MAX_N.  The reduced-cost array D has
+ *    N^2 (N-1)^2 (N-2)^2 entries (8 bytes each in FP64 mode, 4 in FP32 mode);
+ *    creation fails with QAP_ENOMEM if it does not fit in free device memory.
+ *
+ * Compact layouts used by qap_rlt2_read_state and qap_rlt2_lap_values
+ * --------------------------------------------------------------------
+ *  B: N x N, index i*N + j.
+ *  C: N^2 blocks C_ij of (N-1)^2 entries; block (i,j) starts at
+ *     (i*N+j)*(N-1)^2 and holds rows k != i, columns n != j in ascending
+ *     original index: entry (k', n') at k'*(N-1) + n', k' = k - [k > i],
+ *     n' = n - [n > j].  The position of c_ijkn in C is written beta(ijkn).
+ *  D: N^2 (N-1)^2 blocks D_ijkn of (N-2)^2 entries; block D_ijkn is the
+ *     beta(ijkn)-th block and holds rows p not in {i,k} and columns q not in
+ *     {j,n} in ascending original index (Section 4.1).
+ */
+#ifndef QAP_RLT2_H
+#define QAP_RLT2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QAP_RLT2_MAX_N 64
+
+typedef enum {
+    QAP_OK = 0,
+    QAP_EINVAL = -1,   /* bad argument (size, NULL pointer, non-finite input) */
+    QAP_ENOMEM = -2,   /* device or host allocation failed                    */
+    QAP_EDEVICE = -3,  /* a HIP call failed; the message names it             */
+    QAP_ESTATE = -4    /* handle unusable after an earlier device failure     */
+} qap_status;
+
+typedef enum {
+    QAP_FP64 = 0,            /* all reduced costs and transfers in FP64         */
+    QAP_FP32_CERTIFIED = 1   /* FP32 reduced costs, every receiving write
+                                rounded toward -inf, FP64 bound and FP64
+                                certification (see qap_rlt2_certify)           */
+} qap_precision;
+
+typedef struct {
+    int precision;    /* qap_precision                                        */
+    int device;       /* HIP device ordinal; -1 = the calling thread's current */
+    void* stream;     /* hipStream_t to run on; NULL = a stream the handle owns */
+    int trace_level;  /* 0: bound only; 1: per-iteration LB and LB' (default);
+                         2: also the value moved by every concentration of the
+                         most recent iteration (qap_rlt2_lap_values)           */
+    int use_graph;    /* 1 (default): qap_rlt2_ascend replays one captured HIP
+                         graph per iteration; 0: plain launches                */
+} qap_rlt2_opts;
+
+typedef struct qap_rlt2 qap_rlt2;
+
+/* Fill *opts with the defaults (FP64, current device, own stream,
+ * trace_level 1, use_graph 1). */
+qap_status qap_rlt2_default_opts(qap_rlt2_opts* opts);
+
+/* Create a dual-ascent state for the QAP of equation (1) with flows F and
+ * distances D (both N x N host arrays, FP64) and run iteration 0.
+ *
+ * Initial dual (the lines of Algorithm 1 before its loop): LB = 0,
+ * b_ij = f_ii d_jj, c_ijkn = f_ik d_jn, d = 0.  Iteration 0 then concentrates
+ * every C_ij into b_ij and B into LB, which makes LB the Gilmore-Lawler
+ * bound.  Equivalent to qap_rlt2_create_ex(N, F, D, NULL, 0.0, NULL, out). */
+qap_status qap_rlt2_create(int N, const double* F, const double* D, qap_rlt2** out);
+
+/* As qap_rlt2_create, with optional linear costs B0 (N x N host array added
+ * to b_ij, or NULL), a constant added to LB (for a branch-and-bound node whose
+ * fixed assignments contribute a known cost) and options (NULL = defaults). */
+qap_status qap_rlt2_create_ex(int N, const double* F, const double* D,
+                              const double* B0, double constant,
+                              const qap_rlt2_opts* opts, qap_rlt2** out);
+
+/* Run `iters` >= 0 iterations of the Algorithm 1 loop body:
+ *   1. spread B -> C: c_ijkn += b_ij / (N-1), then b = 0        (Section 4.2)
+ *   2. spread C -> D: d_ijknpq += c_ijkn / (N-2), then c = 0     (Section 4.2)
+ *   3. transfer among the six complementary D coefficients of equation (11):
+ *      each becomes their mean                                    (Section 4.3)
+ *   4. concentrate every D_ijkn into c_ijkn by an assignment solve (4.1)
+ *   5. transfer between the complementary pair c_ijkn, c_knij of
+ *      equation (10): both become their mean                    (Section 4.3)
+ *   6. concentrate every C_ij into b_ij                           (4.1)
+ *   7. concentrate B into LB'                                      (4.1)
+ *   8. LB += LB'
+ * Concentration of an n x n block M solves the assignment problem over M,
+ * adds its value S to the parent coefficient and replaces M by the residual
+ * under the canonical optimal dual: the mean of the residuals under the
+ * column-canonical and row-canonical optimal dual points (the greatest dual
+ * vector <= 0 on the optimal dual face, for columns and for rows).
+ * *bound (nullable) receives LB after the last iteration (FP64 mode) or the
+ * certified bound of qap_rlt2_certify (FP32 mode).  Blocks until done. */
+qap_status qap_rlt2_ascend(qap_rlt2* h, int iters, double* bound);
+
+/* Run a single step of the loop body above, for inspection.  Steps 1-3 run
+ * as one fused pass: step must be 3 (steps 1-3), 4, 5, 6 or 7 (steps 7-8). */
+qap_status qap_rlt2_step(qap_rlt2* h, int step);
+
+/* Certified bound, FP64: with m(beta) the minimum of block D_beta,
+ * c~ = c + (N-2) min(0, m); with m'(ij) the minimum of C~_ij,
+ * b~ = b + (N-1) min(0, m'); LB_cert = LB + N min(0, min b~).  LB_cert is a
+ * lower bound on every permutation's objective as represented by the stored
+ * state, whatever the signs of the stored reduced costs. */
+qap_status qap_rlt2_certify(qap_rlt2* h, double* certified);
+
+/* Bound after the most recent iteration and the number of iterations run
+ * (iteration 0 counts as 0; each loop iteration adds 1). */
+qap_status qap_rlt2_bound(qap_rlt2* h, double* lb, int64_t* iterations);
+
+/* Per-iteration trace (trace_level >= 1): entries t = 0 .. *count-1 hold LB
+ * and LB' after iteration t (t = 0 is iteration 0).  At most `capacity`
+ * entries are written; *count receives the number available.  lb and
+ * lbprime may be NULL. */
+qap_status qap_rlt2_trace(qap_rlt2* h, int64_t capacity, int64_t* count,
+                          double* lb, double* lbprime);
+
+/* Values S moved by the concentrations of the most recent iteration (needs
+ * trace_level 2): sD[beta(ijkn)] for D_ijkn -> c_ijkn (N^2 (N-1)^2 entries),
+ * sC[i*N+j] for C_ij -> b_ij (N^2 entries), *sB for B -> LB'.  Each pointer
+ * may be NULL. */
+qap_status qap_rlt2_lap_values(qap_rlt2* h, double* sD, double* sC, double* sB);
+
+/* Copy the current dual state to host FP64 arrays in the compact layouts
+ * above (FP32 state is widened exactly).  Each pointer may be NULL. */
+qap_status qap_rlt2_read_state(qap_rlt2* h, double* lb, double* B, double* C, double* D);
+
+/* Release the handle and all of its device memory.  NULL-safe. */
+void qap_rlt2_destroy(qap_rlt2* h);
+
+/* Batched linear assignment with canonical dual (Section 4.1, the operation
+ * behind every cost concentration).
+ *
+ * batch   number of problems (>= 0).
+ * n       n[b] in [0, 64]: size of problem b.
+ * mat_off problem b's n[b] x n[b] row-major matrix starts at element
+ *         mat_off[b] of `cost`.  Matrices must not overlap.
+ * vec_off problem b's vectors start at element vec_off[b] of `assign` and at
+ *         element 4*vec_off[b] of `duals`; ranges must not overlap.
+ * cost    matrices, FP64 (dtype QAP_FP64) or FP32 (QAP_FP32_CERTIFIED, with
+ *         every residual and value rounded toward -inf).  With
+ *         QAP_LAP_RESIDUAL each matrix is overwritten by its residual.
+ * value   value[b] receives S, the optimal assignment value reached through
+ *         the canonical dual (FP64).
+ * duals   nullable; same dtype as cost: [uc | vc | ur | vr], 4 n[b] values:
+ *         column-canonical point (uc, vc) and row-canonical point (ur, vr).
+ * assign  nullable; assign[r] = column given to row r by an optimal
+ *         assignment (not unique when there are ties).
+ * flags   QAP_LAP_DEVICE: every pointer above is device memory and the call
+ *         is asynchronous on `stream`; otherwise all are host memory and the
+ *         call is synchronous.  QAP_LAP_RESIDUAL: write residuals in place.
+ * stream  hipStream_t or NULL (the null stream). */
+#define QAP_LAP_DEVICE 1
+#define QAP_LAP_RESIDUAL 2
+qap_status qap_lap_solve(int batch, const int32_t* n, const int64_t* mat_off,
+                         const int64_t* vec_off, void* cost, int dtype,
+                         double* value, void* duals, int32_t* assign,
+                         int flags, void* stream);
+
+/* Thread-local description of the most recent failure ("" if none). */
+const char* qap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QAP_RLT2_H */

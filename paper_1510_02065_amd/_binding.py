@@ -1,0 +1,233 @@
+"""ctypes binding of libqap_rlt2.so (include/qap_rlt2.h).
+
+Argument marshalling only: every step of the dual ascent runs in the HIP
+library.  Importing this module does not touch the GPU; the first call loads
+the library and raises if it has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqap_rlt2.so")
+
+QAP_OK, QAP_EINVAL, QAP_ENOMEM, QAP_EDEVICE, QAP_ESTATE = 0, -1, -2, -3, -4
+QAP_FP64, QAP_FP32_CERTIFIED = 0, 1
+QAP_LAP_DEVICE, QAP_LAP_RESIDUAL = 1, 2
+MAX_N = 64
+
+# Every function the header declares, with (restype, argtypes).
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("trace_level", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+SIGNATURES = {
+    "qap_rlt2_default_opts": (ctypes.c_int, [ctypes.POINTER(Opts)]),
+    "qap_rlt2_create": (ctypes.c_int, [ctypes.c_int, _dp, _dp, ctypes.POINTER(_vp)]),
+    "qap_rlt2_create_ex": (ctypes.c_int, [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double,
+                                          ctypes.POINTER(Opts), ctypes.POINTER(_vp)]),
+    "qap_rlt2_ascend": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    "qap_rlt2_step": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "qap_rlt2_certify": (ctypes.c_int, [_vp, _dp]),
+    "qap_rlt2_bound": (ctypes.c_int, [_vp, _dp, _i64p]),
+    "qap_rlt2_trace": (ctypes.c_int, [_vp, ctypes.c_int64, _i64p, _dp, _dp]),
+    "qap_rlt2_lap_values": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "qap_rlt2_read_state": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
+    "qap_rlt2_destroy": (None, [_vp]),
+    "qap_lap_solve": (ctypes.c_int, [ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp,
+                                     ctypes.c_int, _vp]),
+    "qap_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class QapError(RuntimeError):
+    def __init__(self, status, where, message):
+        super().__init__(f"{where} failed with status {status}: {message}")
+        self.status = status
+
+
+def lib():
+    """Load libqap_rlt2.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                               "or python paper_1510_02065_amd/build.py")
+        # One HIP runtime per process: torch ships its own copy of
+        # libamdhip64.so.7 and loads it by file name, so if this library loaded
+        # the system copy first the process would hold two runtimes and torch
+        # would see no GPU.  Importing torch first makes the dynamic loader
+        # resolve this library's libamdhip64.so.7 to torch's already-loaded one.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, where):
+    if status != QAP_OK:
+        raise QapError(status, where, lib().qap_last_error().decode(errors="replace"))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+class Rlt2:
+    """One RLT2 dual-ascent state on the GPU (qap_rlt2_* calls)."""
+
+    def __init__(self, F, D, B0=None, constant=0.0, precision="fp64", trace_level=1,
+                 use_graph=True, device=-1, stream=None):
+        L = lib()
+        F = _f64(F)
+        D = _f64(D)
+        N = F.shape[0]
+        if F.shape != (N, N) or D.shape != (N, N):
+            raise ValueError("F and D must be square and of the same size")
+        B0 = None if B0 is None else _f64(B0)
+        opts = Opts()
+        _check(L.qap_rlt2_default_opts(ctypes.byref(opts)), "qap_rlt2_default_opts")
+        opts.precision = {"fp64": QAP_FP64, "fp32": QAP_FP32_CERTIFIED}[precision]
+        opts.device = device
+        opts.stream = stream
+        opts.trace_level = trace_level
+        opts.use_graph = 1 if use_graph else 0
+        h = _vp()
+        _check(L.qap_rlt2_create_ex(N, _dptr(F), _dptr(D), _dptr(B0), float(constant),
+                                    ctypes.byref(opts), ctypes.byref(h)), "qap_rlt2_create_ex")
+        self._h = h
+        self.N = N
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qap_rlt2_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def ascend(self, iters=1):
+        out = ctypes.c_double()
+        _check(lib().qap_rlt2_ascend(self._h, int(iters), ctypes.byref(out)), "qap_rlt2_ascend")
+        return out.value
+
+    def step(self, step):
+        _check(lib().qap_rlt2_step(self._h, int(step)), "qap_rlt2_step")
+
+    def certify(self):
+        out = ctypes.c_double()
+        _check(lib().qap_rlt2_certify(self._h, ctypes.byref(out)), "qap_rlt2_certify")
+        return out.value
+
+    def bound(self):
+        lb = ctypes.c_double()
+        it = ctypes.c_int64()
+        _check(lib().qap_rlt2_bound(self._h, ctypes.byref(lb), ctypes.byref(it)), "qap_rlt2_bound")
+        return lb.value, it.value
+
+    def trace(self):
+        cnt = ctypes.c_int64()
+        _check(lib().qap_rlt2_trace(self._h, 0, ctypes.byref(cnt), None, None), "qap_rlt2_trace")
+        lb = np.empty(cnt.value)
+        lbp = np.empty(cnt.value)
+        _check(lib().qap_rlt2_trace(self._h, cnt.value, ctypes.byref(cnt), _dptr(lb), _dptr(lbp)),
+               "qap_rlt2_trace")
+        return lb, lbp
+
+    def lap_values(self):
+        N = self.N
+        sD = np.empty(N * N * (N - 1) * (N - 1))
+        sC = np.empty(N * N)
+        sB = np.empty(1)
+        _check(lib().qap_rlt2_lap_values(self._h, _dptr(sD), _dptr(sC), _dptr(sB)), "qap_rlt2_lap_values")
+        return sD, sC, float(sB[0])
+
+    def read_state(self, want_D=True):
+        N = self.N
+        B = np.empty(N * N)
+        C = np.empty(N * N * (N - 1) ** 2)
+        D = np.empty(N * N * (N - 1) ** 2 * (N - 2) ** 2) if want_D else None
+        lb = np.empty(1)
+        _check(lib().qap_rlt2_read_state(self._h, _dptr(lb), _dptr(B), _dptr(C), _dptr(D)),
+               "qap_rlt2_read_state")
+        return float(lb[0]), B, C, D
+
+
+def lap_solve(mats, residual=False, want_duals=True, want_assign=True):
+    """Solve a batch of square host matrices (list of 2-D arrays, FP64).
+
+    Returns dict with 'value' (S per problem), 'duals' (list of (4, n)
+    arrays: uc, vc, ur, vr), 'assign' (list of row->column arrays) and, with
+    residual=True, 'residual' (list of n x n arrays)."""
+    mats = [_f64(m) for m in mats]
+    batch = len(mats)
+    n = np.array([m.shape[0] for m in mats], dtype=np.int32)
+    mat_off = np.zeros(batch, dtype=np.int64)
+    vec_off = np.zeros(batch, dtype=np.int64)
+    if batch:
+        mat_off[1:] = np.cumsum(n.astype(np.int64) ** 2)[:-1]
+        vec_off[1:] = np.cumsum(n.astype(np.int64))[:-1]
+    total_m = int((n.astype(np.int64) ** 2).sum())
+    total_v = int(n.sum())
+    cost = np.concatenate([m.ravel() for m in mats]) if batch else np.zeros(0)
+    cost = np.ascontiguousarray(cost, dtype=np.float64)
+    value = np.empty(batch)
+    duals = np.empty(4 * total_v) if want_duals else None
+    assign = np.empty(total_v, dtype=np.int32) if want_assign else None
+    flags = QAP_LAP_RESIDUAL if residual else 0
+    _check(lib().qap_lap_solve(batch, n.ctypes.data, mat_off.ctypes.data, vec_off.ctypes.data,
+                               cost.ctypes.data if total_m else None, QAP_FP64, value.ctypes.data,
+                               None if duals is None else duals.ctypes.data,
+                               None if assign is None else assign.ctypes.data, flags, None),
+           "qap_lap_solve")
+    out = {"value": value}
+    if want_duals:
+        out["duals"] = [duals[4 * vec_off[b]: 4 * vec_off[b] + 4 * n[b]].reshape(4, n[b]) for b in range(batch)]
+    if want_assign:
+        out["assign"] = [assign[vec_off[b]: vec_off[b] + n[b]] for b in range(batch)]
+    if residual:
+        out["residual"] = [cost[mat_off[b]: mat_off[b] + n[b] ** 2].reshape(n[b], n[b]) for b in range(batch)]
+    return out
+
+
+def lap_solve_device(n, mat_off, vec_off, cost, value, duals=None, assign=None, residual=False,
+                     stream=None, fp32=False):
+    """Device-pointer batch: every argument is a torch CUDA tensor (or None);
+    the call is asynchronous on `stream` (a torch.cuda.Stream or None)."""
+    ptr = (lambda t: None if t is None else t.data_ptr())
+    flags = QAP_LAP_DEVICE | (QAP_LAP_RESIDUAL if residual else 0)
+    sp = None if stream is None else stream.cuda_stream
+    _check(lib().qap_lap_solve(int(n.numel()), ptr(n), ptr(mat_off), ptr(vec_off), ptr(cost),
+                               QAP_FP32_CERTIFIED if fp32 else QAP_FP64, ptr(value), ptr(duals),
+                               ptr(assign), flags, sp), "qap_lap_solve")
