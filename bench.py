@@ -29,6 +29,7 @@ def parse():
     ap.add_argument("--kernel-iters", type=int, default=3,
                     help="extra step-by-step iterations used to time each kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the certified FP32 leg")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="oracle iterations in the CPU baseline (0: pick ~15 s of work)")
     return ap.parse_args()
@@ -105,6 +106,28 @@ def main():
     iter_frac = alg_bytes * it_s / 1e9 / HBM_PEAK_GBS
 
     lb_trace, _ = g.trace()
+
+    # Certified FP32 leg on the same instance and iteration count.
+    f32 = None
+    if not args.no_fp32:
+        h = Rlt2(F, D, precision="fp32", trace_level=1, use_graph=True, device=0, stream=stream.cuda_stream)
+        h.ascend(args.warmup)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        cert = h.ascend(args.steps)
+        b.record(stream)
+        b.synchronize()
+        ms32 = a.elapsed_time(b) / args.steps
+        ref = lb_trace[args.warmup + args.steps]
+        f32 = {"iters_per_s": 1000.0 / ms32, "laps_per_s": laps_per_iter * 1000.0 / ms32,
+               "ms_per_step": ms32, "certified_bound": cert,
+               "rel_err_vs_fp64_gpu": abs(cert - ref) / abs(ref),
+               "certified_below_fp64": bool(cert <= ref),
+               "speedup_vs_fp64": ms_per_step / ms32,
+               "iteration_hbm_fraction": 2.0 * nD * 4 * (1000.0 / ms32) / 1e9 / HBM_PEAK_GBS}
+        h.close()
     rel_err = None
     gold = os.path.join(ROOT, "tests", "golden", f"clustered{N}_seed{args.seed}_oracle_lb.json")
     total_iters = args.warmup + args.steps
@@ -137,6 +160,7 @@ def main():
         "bound_iteration": total_iters,
         "iteration_hbm_fraction": iter_frac,
         "kernel_ms": {names[s]: round(v, 4) for s, v in dur.items()},
+        "fp32_certified": f32,
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
     }

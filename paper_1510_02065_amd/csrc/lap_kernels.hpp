@@ -23,10 +23,10 @@ __global__ __launch_bounds__(64) void k_lap_family(T* __restrict__ blocks, int64
     const size_t sb = SegLds<T, SEG>::bytes(n);
     unsigned char* base = smem + seg * sb;
     T* Ms = reinterpret_cast<T*>(base);
-    const size_t mb = (((size_t)n * n * sizeof(T)) + 15) & ~(size_t)15;
+    const size_t mb = SegLds<T, SEG>::mat_bytes(n);
     int* sig_s = reinterpret_cast<int*>(base + mb);
-    T* va_s = reinterpret_cast<T*>(base + mb + SEG * sizeof(int));
-    T* vb_s = va_s + SEG;
+    double* va_s = reinterpret_cast<double*>(base + mb + SEG * sizeof(int));
+    double* vb_s = va_s + SEG;
 
     T* blk = blocks + (active ? b : 0) * bstride;
     if (active)
@@ -35,7 +35,10 @@ __global__ __launch_bounds__(64) void k_lap_family(T* __restrict__ blocks, int64
     const double S = lap_concentrate_seg<T, SEG>(Ms, active ? n : 0, sig_s, va_s, vb_s,
                                                  active ? blk : nullptr, nullptr, nullptr);
     if (active && lane == 0) {
-        parent[b] = parent[b] + (T)S;
+        if constexpr (sizeof(T) == 8)
+            parent[b] = parent[b] + S;
+        else
+            parent[b] = to_float_down(add_down((double)parent[b], S));
         if (values) values[b] = S;
     }
 }
@@ -56,17 +59,18 @@ __global__ __launch_bounds__(64) void k_lap_B(T* __restrict__ B, int n, double* 
     const size_t sb = SegLds<T, SEG>::bytes(n);
     unsigned char* base = smem + seg * sb;
     T* Ms = reinterpret_cast<T*>(base);
-    const size_t mb = (((size_t)n * n * sizeof(T)) + 15) & ~(size_t)15;
+    const size_t mb = SegLds<T, SEG>::mat_bytes(n);
     int* sig_s = reinterpret_cast<int*>(base + mb);
-    T* va_s = reinterpret_cast<T*>(base + mb + SEG * sizeof(int));
-    T* vb_s = va_s + SEG;
+    double* va_s = reinterpret_cast<double*>(base + mb + SEG * sizeof(int));
+    double* vb_s = va_s + SEG;
     if (active)
         for (int e = lane; e < n * n; e += SEG) Ms[e] = B[e];
     __syncthreads();
     const double S = lap_concentrate_seg<T, SEG>(Ms, active ? n : 0, sig_s, va_s, vb_s,
                                                  active ? B : nullptr, nullptr, nullptr);
     if (active && lane == 0) {
-        const double L = lb[0] + S;
+        // FP32 certified mode accumulates the bound rounding toward -inf.
+        const double L = (sizeof(T) == 4) ? add_down(lb[0], S) : lb[0] + S;
         lb[0] = L;
         lb[1] = S;
         if (values) values[0] = S;
@@ -103,10 +107,10 @@ __global__ __launch_bounds__(64) void k_lap_batch(int batch, const int32_t* __re
     const size_t sb = SegLds<T, SEG>::bytes(SEG);
     unsigned char* base = smem + seg * sb;
     T* Ms = reinterpret_cast<T*>(base);
-    const size_t mb = (((size_t)SEG * SEG * sizeof(T)) + 15) & ~(size_t)15;
+    const size_t mb = SegLds<T, SEG>::mat_bytes(SEG);
     int* sig_s = reinterpret_cast<int*>(base + mb);
-    T* va_s = reinterpret_cast<T*>(base + mb + SEG * sizeof(int));
-    T* vb_s = va_s + SEG;
+    double* va_s = reinterpret_cast<double*>(base + mb + SEG * sizeof(int));
+    double* vb_s = va_s + SEG;
     T* mat = (b < batch && !bad) ? cost + mat_off[b] : nullptr;
     const int64_t vo = (b < batch && !bad) ? vec_off[b] : 0;
     for (int e = lane; e < n * n; e += SEG) Ms[e] = mat[e];

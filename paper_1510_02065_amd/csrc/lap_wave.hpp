@@ -29,27 +29,95 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rlt2_kernels.hpp"
+
 namespace qap {
 
 template <typename T> __device__ __forceinline__ T inf_of();
 template <> __device__ __forceinline__ double inf_of<double>() { return __builtin_huge_val(); }
 template <> __device__ __forceinline__ float inf_of<float>() { return __builtin_huge_valf(); }
 
-// Segment-wide collectives.  All lanes of a segment must be active when one of
-// these is called; segments of the same wave are independent.
+// ---- cross-lane primitives ---------------------------------------------------
+// Reductions use no LDS.  DPP controls (gfx9 encoding): quad_perm(1,0,3,2)
+// pairs lane^1, quad_perm(2,3,0,1) pairs lane^2, row_half_mirror reverses 8
+// lanes and row_mirror 16 lanes.  After the two quad swaps every lane of a
+// quad holds the quad's value; each mirror then combines a group with its
+// neighbour, so the four steps all-reduce 16 lanes.  permlane16_swap and
+// permlane32_swap (gfx950) called with the same register twice return, in
+// their two results, the lane's own value and the value 16 (32) lanes away in
+// some order, which is all a commutative reduction needs.
+enum : int { kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140 };
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) { return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true); }
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) { return __int_as_float(dpp_i<CTRL>(__float_as_int(x))); }
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+    const int lo = dpp_i<CTRL>(__double2loint(x));
+    const int hi = dpp_i<CTRL>(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+template <int HALF>
+__device__ __forceinline__ void swap_pair(float x, float& a, float& b) {
+    const unsigned u = __float_as_uint(x);
+    if constexpr (HALF == 16) {
+        auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        a = __uint_as_float(r[0]);
+        b = __uint_as_float(r[1]);
+    } else {
+        auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        a = __uint_as_float(r[0]);
+        b = __uint_as_float(r[1]);
+    }
+}
+template <int HALF>
+__device__ __forceinline__ void swap_pair(double x, double& a, double& b) {
+    const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+    if constexpr (HALF == 16) {
+        auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        a = __hiloint2double((int)rh[0], (int)rl[0]);
+        b = __hiloint2double((int)rh[1], (int)rl[1]);
+    } else {
+        auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        a = __hiloint2double((int)rh[0], (int)rl[0]);
+        b = __hiloint2double((int)rh[1], (int)rl[1]);
+    }
+}
+
+__device__ __forceinline__ float tmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double tmin(double a, double b) { return __builtin_fmin(a, b); }
+
+// Segment-wide collectives for segments of SEG lanes (LPW = 64/SEG segments
+// per wave).  All lanes of a segment must be active when one is called;
+// segments are independent of each other.
 template <int SEG>
 struct Seg {
     static_assert(SEG == 8 || SEG == 16 || SEG == 32 || SEG == 64, "segment size");
+    static constexpr int LPW = 64 / SEG;
     __device__ __forceinline__ static int lane() { return threadIdx.x & (SEG - 1); }
+    __device__ __forceinline__ static int seg() { return (threadIdx.x & 63) / SEG; }
     __device__ __forceinline__ static int base() { return (threadIdx.x & 63) & ~(SEG - 1); }
 
     // min over the segment; every lane receives the same value.
     template <typename T>
     __device__ __forceinline__ static T min(T x) {
-#pragma unroll
-        for (int m = 1; m < SEG; m <<= 1) {
-            T y = __shfl_xor(x, m, 64);
-            x = (y < x) ? y : x;
+        x = tmin(x, dpp<kDppXor1>(x));
+        x = tmin(x, dpp<kDppXor2>(x));
+        x = tmin(x, dpp<kDppHalfMirror>(x));
+        if constexpr (SEG >= 16) x = tmin(x, dpp<kDppMirror>(x));
+        if constexpr (SEG >= 32) {
+            T a, b;
+            swap_pair<16>(x, a, b);
+            x = tmin(a, b);
+        }
+        if constexpr (SEG >= 64) {
+            T a, b;
+            swap_pair<32>(x, a, b);
+            x = tmin(a, b);
         }
         return x;
     }
@@ -57,30 +125,128 @@ struct Seg {
     // lane receives bitwise the same value.
     template <typename T>
     __device__ __forceinline__ static T sum(T x) {
-#pragma unroll
-        for (int m = 1; m < SEG; m <<= 1) x = x + __shfl_xor(x, m, 64);
+        x = x + dpp<kDppXor1>(x);
+        x = x + dpp<kDppXor2>(x);
+        x = x + dpp<kDppHalfMirror>(x);
+        if constexpr (SEG >= 16) x = x + dpp<kDppMirror>(x);
+        if constexpr (SEG >= 32) {
+            T a, b;
+            swap_pair<16>(x, a, b);
+            x = a + b;
+        }
+        if constexpr (SEG >= 64) {
+            T a, b;
+            swap_pair<32>(x, a, b);
+            x = a + b;
+        }
         return x;
     }
-    // lowest segment lane with pred true (SEG if none).
-    __device__ __forceinline__ static int first(bool pred) {
-        unsigned long long m = __ballot(pred);
-        unsigned long long s = (SEG == 64) ? m : ((m >> base()) & ((1ull << SEG) - 1ull));
-        return s ? (int)__builtin_ctzll(s) : SEG;
+
+    // sum over the segment with every addition rounded toward -inf; TwoSum
+    // is exact and symmetric, so every lane receives the same value.
+    __device__ __forceinline__ static double sum_down(double x) {
+        x = add_down(x, dpp<kDppXor1>(x));
+        x = add_down(x, dpp<kDppXor2>(x));
+        x = add_down(x, dpp<kDppHalfMirror>(x));
+        if constexpr (SEG >= 16) x = add_down(x, dpp<kDppMirror>(x));
+        if constexpr (SEG >= 32) {
+            double a, b;
+            swap_pair<16>(x, a, b);
+            x = add_down(a, b);
+        }
+        if constexpr (SEG >= 64) {
+            double a, b;
+            swap_pair<32>(x, a, b);
+            x = add_down(a, b);
+        }
+        return x;
+    }
+
+    // Per-segment scalar indices, kept in scalar registers.
+    struct Idx {
+        int s[LPW];
+    };
+    // lowest lane of each segment with pred true (SEG if none).
+    __device__ __forceinline__ static Idx first(bool pred) {
+        const unsigned long long m = __ballot(pred);
+        Idx r;
+#pragma unroll
+        for (int g = 0; g < LPW; ++g) {
+            const unsigned long long sm = (SEG == 64) ? m : ((m >> (g * SEG)) & ((1ull << SEG) - 1ull));
+            r.s[g] = sm ? (int)__builtin_ctzll(sm) : SEG;
+        }
+        return r;
+    }
+    // this lane's segment's entry of a per-segment scalar.
+    __device__ __forceinline__ static int mine(const Idx& x) {
+        int r = x.s[0];
+#pragma unroll
+        for (int g = 1; g < LPW; ++g) r = (seg() == g) ? x.s[g] : r;
+        return r;
+    }
+    // value of x at lane idx of each segment, as a per-segment scalar.
+    __device__ __forceinline__ static Idx at(int x, const Idx& idx) {
+        Idx r;
+#pragma unroll
+        for (int g = 0; g < LPW; ++g) r.s[g] = __builtin_amdgcn_readlane(x, g * SEG + (idx.s[g] & (SEG - 1)));
+        return r;
+    }
+    // value of x at lane idx of this lane's segment (broadcast by readlane).
+    __device__ __forceinline__ static int bcast(int x, const Idx& idx) { return mine(at(x, idx)); }
+    __device__ __forceinline__ static float bcast(float x, const Idx& idx) {
+        return __int_as_float(bcast(__float_as_int(x), idx));
+    }
+    __device__ __forceinline__ static double bcast(double x, const Idx& idx) {
+        const int lo = bcast(__double2loint(x), idx);
+        const int hi = bcast(__double2hiint(x), idx);
+        return __hiloint2double(hi, lo);
     }
     // value of x held by segment lane src (src may differ per lane).
     template <typename T>
     __device__ __forceinline__ static T read(T x, int src) { return __shfl(x, base() + src, 64); }
 };
 
-// Per-segment LDS working set, laid out as [matrix n*n | sig SEG | vecA SEG | vecB SEG].
+// Per-segment LDS working set, laid out as
+// [matrix n*n of T | sig: SEG ints | vecA: SEG doubles | vecB: SEG doubles].
 template <typename T, int SEG>
 struct SegLds {
+    __host__ __device__ static size_t mat_bytes(int n) {
+        return (((size_t)n * n * sizeof(T)) + 15) & ~(size_t)15;
+    }
     __host__ __device__ static size_t bytes(int n) {
-        size_t m = (size_t)n * n * sizeof(T);
-        m = (m + 15) & ~(size_t)15;
-        return m + SEG * (sizeof(int) + 2 * sizeof(T));
+        return mat_bytes(n) + SEG * (sizeof(int) + 2 * sizeof(double));
     }
 };
+
+// Row-canonical point, lanes = rows: u^r = u + shortest distances in the row
+// graph, whose arc s -> r costs the reduced cost M[r][sigma(s)] - u_r -
+// v_sigma(s) >= 0, from label -u_r at every row (one dense Dijkstra pass).
+template <typename T, int SEG>
+__device__ __forceinline__ T row_canonical(const T* __restrict__ M, int n, int lane, bool ok, int sig,
+                                           T urow, T v)
+{
+    using S = Seg<SEG>;
+    using Idx = typename S::Idx;
+    const T INF = inf_of<T>();
+    T distr = ok ? -urow : INF;
+    bool doner = !ok;
+    for (int s = 0; s < n; ++s) {
+        const T cand = doner ? INF : distr;
+        const T dmin = S::min(cand);
+        const Idx rs_ = S::first(!doner && cand == dmin);
+        const int srow = S::mine(rs_);
+        if (srow >= n) break;
+        const Idx cs = S::at(sig, rs_);
+        const int csl = S::mine(cs);
+        const T vcs = S::bcast(v, cs);
+        if (lane == srow) doner = true;
+        if (!doner) {
+            const T nd = dmin + ((M[lane * n + csl] - urow) - vcs);
+            if (nd < distr) distr = nd;
+        }
+    }
+    return urow + distr;
+}
 
 // Solve, canonicalise and write residuals for the n x n matrix M (in LDS).
 //   n        problem size for this segment (0 <= n <= SEG; segment-uniform).
@@ -93,63 +259,68 @@ struct SegLds {
 // uniform control flow (it contains block barriers; launch one wave per
 // workgroup).
 template <typename T, int SEG>
-__device__ double lap_concentrate_seg(const T* __restrict__ M, int n, int* __restrict__ sig_s,
-                                      T* __restrict__ va_s, T* __restrict__ vb_s,
+__device__ __forceinline__ double lap_concentrate_seg(const T* __restrict__ M, int n, int* __restrict__ sig_s,
+                                      double* __restrict__ va_s, double* __restrict__ vb_s,
                                       T* __restrict__ R, T* __restrict__ duals,
                                       int32_t* __restrict__ assign)
 {
     using S = Seg<SEG>;
+    using Idx = typename S::Idx;
     const int lane = S::lane();
     const bool ok = lane < n;
     const T INF = inf_of<T>();
 
     // ---- Hungarian method, shortest augmenting paths -----------------------
     // Column lane j keeps: v (column dual), p (row matched to column j or -1),
-    // ucol (dual of row p).  The row being inserted has dual ufree.
+    // ucol (dual of row p).  Inserting row i runs Dijkstra over columns with
+    // absolute tentative distances `dist` (reduced costs are >= 0); duals are
+    // only shifted when the search reaches an unmatched column, by
+    // D* - dist_j for every scanned column j (Jonker-Volgenant form).
     T v = 0, ucol = 0;
     int p = -1;
     for (int i = 0; i < n; ++i) {
-        T minv = INF;   // tentative reduced distance to column j
-        int way = -1;   // previous column on the shortest path (-1: the new row)
+        T dist = INF;   // tentative distance from row i to column j
+        int way = -1;   // previous column on the shortest path (-1: row i)
         bool used = false;
-        T ufree = 0;
         int i0 = i;     // row being scanned
-        T ui0 = 0;      // its dual
+        T ui0 = 0;      // its dual (row i has dual 0 before insertion)
+        T d0 = 0;       // distance at which row i0 was reached
         int j0 = -1;    // column through which row i0 was reached
         int jend = -1;
-        // Each pass marks one more column as scanned, so a well-formed search
-        // ends within n passes; the bound also ends it on non-finite input.
+        T dend = 0;
+        // Each pass scans one more column, so a well-formed search ends within
+        // n passes; the bound also ends it on non-finite input.
         for (int pass = 0; pass <= n; ++pass) {
             if (ok && !used) {
-                T cur = (M[i0 * n + lane] - ui0) - v;
-                if (cur < minv) {
-                    minv = cur;
+                const T cur = d0 + ((M[i0 * n + lane] - ui0) - v);
+                if (cur < dist) {
+                    dist = cur;
                     way = j0;
                 }
             }
-            const T cand = (ok && !used) ? minv : INF;
-            const T delta = S::min(cand);
-            const int j1 = S::first(ok && !used && cand == delta);
+            const T cand = (ok && !used) ? dist : INF;
+            const T dmin = S::min(cand);
+            const Idx j1s = S::first(ok && !used && cand == dmin);
+            const int j1 = S::mine(j1s);
             if (j1 >= n) break;   // no candidate: non-finite costs
-            if (ok) {
-                if (used) {
-                    v -= delta;
-                    ucol += delta;
-                } else {
-                    minv -= delta;
-                }
-            }
-            ufree += delta;
-            const int pj = S::read(p, j1);
-            const T uj = S::read(ucol, j1);
+            const int pj = S::bcast(p, j1s);
+            const T uj = S::bcast(ucol, j1s);
             if (pj < 0) {
                 jend = j1;
+                dend = dmin;
                 break;
             }
             if (lane == j1) used = true;
             j0 = j1;
             i0 = pj;
             ui0 = uj;
+            d0 = dmin;
+        }
+        // Dual shift of the scanned tree.
+        if (ok && used) {
+            const T sh = dend - dist;
+            v -= sh;
+            ucol += sh;
         }
         // Flip the path: every column on it takes the row (and row dual) of
         // its predecessor column; the first one takes the new row.
@@ -163,7 +334,7 @@ __device__ double lap_concentrate_seg(const T* __restrict__ M, int n, int* __res
         const T uw = S::read(ucol, src);
         if (onpath) {
             p = (way >= 0) ? pw : i;
-            ucol = (way >= 0) ? uw : ufree;
+            ucol = (way >= 0) ? uw : dend;
         }
     }
 
@@ -179,10 +350,11 @@ __device__ double lap_concentrate_seg(const T* __restrict__ M, int n, int* __res
     for (int s = 0; s < n; ++s) {
         const T cand = done ? INF : dist;
         const T dmin = S::min(cand);
-        const int c = S::first(!done && cand == dmin);
+        const Idx cs_ = S::first(!done && cand == dmin);
+        const int c = S::mine(cs_);
         if (c >= n) break;
-        const int r = S::read(p, c);
-        const T ur = S::read(ucol, c);
+        const int r = S::bcast(p, cs_);
+        const T ur = S::bcast(ucol, cs_);
         if (lane == c) done = true;
         if (!done) {
             const T nd = dmin + ((M[r * n + lane] - ur) - v);
@@ -190,70 +362,88 @@ __device__ double lap_concentrate_seg(const T* __restrict__ M, int n, int* __res
         }
     }
     const T vc = v + dist;
-    if (ok) va_s[lane] = vc;
-    __syncthreads();
-    T uc = INF;   // lane as row r
-    if (ok) {
-        for (int q = 0; q < n; ++q) {
-            const T t = M[lane * n + q] - va_s[q];
-            uc = (t < uc) ? t : uc;
-        }
-    }
 
-    // ---- row-canonical point (lanes = rows) ---------------------------------
-    T distr = ok ? -urow : INF;
-    bool doner = !ok;
-    for (int s = 0; s < n; ++s) {
-        const T cand = doner ? INF : distr;
-        const T dmin = S::min(cand);
-        const int srow = S::first(!doner && cand == dmin);
-        if (srow >= n) break;
-        const int cs = S::read(sig, srow);
-        const T vcs = S::read(v, cs);
-        if (lane == srow) doner = true;
-        if (!doner) {
-            const T nd = dmin + ((M[lane * n + cs] - urow) - vcs);
-            if (nd < distr) distr = nd;
+    if constexpr (sizeof(T) == 8) {
+        // ---- FP64: residual = mean of the residuals under the two points ----
+        if (ok) va_s[lane] = vc;
+        __syncthreads();
+        T uc = INF;   // lane as row r
+        if (ok) {
+            for (int q = 0; q < n; ++q) uc = tmin(uc, M[lane * n + q] - (T)va_s[q]);
         }
-    }
-    const T ur = urow + distr;
-    __syncthreads();
-    if (ok) vb_s[lane] = ur;
-    __syncthreads();
-    T vr = INF;   // lane as column q
-    if (ok) {
-        for (int r = 0; r < n; ++r) {
-            const T t = M[r * n + lane] - vb_s[r];
-            vr = (t < vr) ? t : vr;
+        const T ur = row_canonical<T, SEG>(M, n, lane, ok, sig, urow, v);
+        __syncthreads();
+        if (ok) vb_s[lane] = ur;
+        __syncthreads();
+        T vr = INF;   // lane as column q
+        if (ok) {
+            for (int r = 0; r < n; ++r) vr = tmin(vr, M[r * n + lane] - (T)vb_s[r]);
         }
-    }
-    __syncthreads();
-    if (ok) va_s[lane] = uc;
-    __syncthreads();
-
-    // ---- residual and transferred value -------------------------------------
-    if (R != nullptr && ok) {
-        for (int r = 0; r < n; ++r) {
-            const T m = M[r * n + lane];
-            const T r1 = (m - vc) - va_s[r];
-            const T r2 = (m - vb_s[r]) - vr;
-            R[r * n + lane] = (T)0.5 * (r1 + r2);
+        __syncthreads();
+        if (ok) va_s[lane] = uc;
+        __syncthreads();
+        if (R != nullptr && ok) {
+            for (int r = 0; r < n; ++r) {
+                const T m = M[r * n + lane];
+                const T r1 = (m - vc) - (T)va_s[r];
+                const T r2 = (m - (T)vb_s[r]) - vr;
+                R[r * n + lane] = (T)0.5 * (r1 + r2);
+            }
         }
+        if (duals != nullptr && ok) {
+            duals[lane] = uc;
+            duals[n + lane] = vc;
+            duals[2 * n + lane] = ur;
+            duals[3 * n + lane] = vr;
+        }
+        if (assign != nullptr && ok) assign[lane] = sig;
+        const T suc = S::sum(ok ? uc : (T)0);
+        const T svc = S::sum(ok ? vc : (T)0);
+        const T sur = S::sum(ok ? ur : (T)0);
+        const T svr = S::sum(ok ? vr : (T)0);
+        __syncthreads();
+        return 0.5 * ((suc + svc) + (sur + svr));
+    } else {
+        // ---- FP32 certified: the duals are completed in FP64 rounding toward
+        // -inf, which keeps them feasible (u_r + v_q <= M_rq exactly).  With
+        // U = (uc + ur)/2 and V = (vc + vr)/2 the residual M - U - V (the same
+        // value as the mean of the two residuals) is then >= 0, and each entry
+        // and S = sum U + sum V are rounded down once.
+        if (ok) va_s[lane] = (double)vc;
+        __syncthreads();
+        double uc = __builtin_huge_val();   // lane as row r
+        if (ok) {
+            for (int q = 0; q < n; ++q) uc = __builtin_fmin(uc, sub_down((double)M[lane * n + q], va_s[q]));
+        }
+        const T ur = row_canonical<T, SEG>(M, n, lane, ok, sig, urow, v);
+        __syncthreads();
+        if (ok) vb_s[lane] = (double)ur;
+        __syncthreads();
+        double vr = __builtin_huge_val();   // lane as column q
+        if (ok) {
+            for (int r = 0; r < n; ++r) vr = __builtin_fmin(vr, sub_down((double)M[r * n + lane], vb_s[r]));
+        }
+        const double U = ok ? 0.5 * add_down(uc, (double)ur) : 0.0;    // lane as row
+        const double V = ok ? 0.5 * add_down((double)vc, vr) : 0.0;    // lane as column
+        __syncthreads();
+        if (ok) va_s[lane] = U;
+        __syncthreads();
+        if (R != nullptr && ok) {
+            for (int r = 0; r < n; ++r)
+                R[r * n + lane] = to_float_down(sub_down(sub_down((double)M[r * n + lane], V), va_s[r]));
+        }
+        if (duals != nullptr && ok) {
+            duals[lane] = (T)uc;
+            duals[n + lane] = vc;
+            duals[2 * n + lane] = ur;
+            duals[3 * n + lane] = (T)vr;
+        }
+        if (assign != nullptr && ok) assign[lane] = sig;
+        const double su = S::sum_down(U);
+        const double sv = S::sum_down(V);
+        __syncthreads();
+        return add_down(su, sv);
     }
-    if (duals != nullptr && ok) {
-        duals[lane] = uc;
-        duals[n + lane] = vc;
-        duals[2 * n + lane] = ur;
-        duals[3 * n + lane] = vr;
-    }
-    if (assign != nullptr && ok) assign[lane] = sig;
-
-    const T suc = S::sum(ok ? uc : (T)0);
-    const T svc = S::sum(ok ? vc : (T)0);
-    const T sur = S::sum(ok ? ur : (T)0);
-    const T svr = S::sum(ok ? vr : (T)0);
-    __syncthreads();
-    return 0.5 * ((double)(suc + svc) + (double)(sur + svr));
 }
 
 }  // namespace qap

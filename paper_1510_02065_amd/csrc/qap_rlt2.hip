@@ -147,6 +147,9 @@ struct qap_rlt2 {
     double* dTrace = nullptr;   // kTraceCap x (LB, LB')
     long long* dCounter = nullptr;
     int* dTri = nullptr;
+    double* dCt = nullptr;      // certification: c~ per C entry
+    double* dBt = nullptr;      // certification: b~ per B entry
+    double* dCert = nullptr;    // certification result
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     std::vector<double> tLB, tLBp;
@@ -171,9 +174,11 @@ hipError_t enqueue_step(qap_rlt2* h, int step)
         hipLaunchKernelGGL((qap::k_spread_prep<T>), dim3(grid_for(h->nC, 256)), dim3(256), 0, st, C, B, CC, N);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        const int64_t work = std::max<int64_t>(h->ngroups, h->nB);
-        hipLaunchKernelGGL((qap::k_sweep<T>), dim3(grid_for(work, 256)), dim3(256), 0, st, D, CC, B, h->dTri, N,
-                           h->ldD, h->ngroups);
+        const int ntri = N * (N - 1) * (N - 2) / 6;
+        const int wpt = (N * (N - 1) * (N - 2) + 255) / 256;
+        const unsigned grid = (unsigned)(8 * ((ntri + 7) / 8) * wpt);
+        hipLaunchKernelGGL((qap::k_sweep<T>), dim3(grid), dim3(256), 0, st, D, CC, B, h->dTri, N, h->ldD, ntri,
+                           wpt);
         return hipGetLastError();
     }
     case 4:
@@ -189,6 +194,24 @@ hipError_t enqueue_step(qap_rlt2* h, int step)
     default:
         return hipErrorInvalidValue;
     }
+}
+
+template <typename T>
+hipError_t enqueue_certify(qap_rlt2* h)
+{
+    const int N = h->N, n2 = N - 2;
+    hipStream_t st = h->stream;
+    hipLaunchKernelGGL((qap::k_cert_D<T>), dim3(grid_for(h->nblkD, 4)), dim3(256), 0, st,
+                       static_cast<const T*>(h->dD), h->ldD, n2 * n2, h->nblkD, static_cast<const T*>(h->dC),
+                       h->dCt, N);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((qap::k_cert_C<T>), dim3(grid_for(h->nB, 4)), dim3(256), 0, st, h->dCt,
+                       static_cast<const T*>(h->dB), h->dBt, N);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(qap::k_cert_final, dim3(1), dim3(64), 0, st, h->dBt, N, h->dLB, h->dCert);
+    return hipGetLastError();
 }
 
 hipError_t enqueue_step_any(qap_rlt2* h, int step)
@@ -234,7 +257,7 @@ void release(qap_rlt2* h)
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
     void* ptrs[] = {h->dB, h->dC, h->dD, h->dCC, h->dLB, h->dValD, h->dValC, h->dValB, h->dTrace,
-                    h->dCounter, h->dTri};
+                    h->dCounter, h->dTri, h->dCt, h->dBt, h->dCert};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -292,7 +315,6 @@ qap_status qap_rlt2_create_ex(int N, const double* F, const double* Dm, const do
     if (opts) o = *opts;
     if (o.precision != QAP_FP64 && o.precision != QAP_FP32_CERTIFIED)
         return fail(QAP_EINVAL, "unknown precision");
-    if (o.precision != QAP_FP64) return fail(QAP_EINVAL, "FP32 certified mode is not available in this build");
 
     qap_rlt2* h = new (std::nothrow) qap_rlt2();
     if (!h) return fail(QAP_ENOMEM, "host allocation failed");
@@ -350,6 +372,9 @@ qap_status qap_rlt2_create_ex(int N, const double* F, const double* Dm, const do
     CK(hipMalloc(&h->dLB, 2 * sizeof(double)));
     CK(hipMalloc(&h->dTrace, 2 * kTraceCap * sizeof(double)));
     CK(hipMalloc(&h->dCounter, sizeof(long long)));
+    CK(hipMalloc(&h->dCt, h->nC * sizeof(double)));
+    CK(hipMalloc(&h->dBt, h->nB * sizeof(double)));
+    CK(hipMalloc(&h->dCert, sizeof(double)));
     if (h->trace_level >= 2) {
         CK(hipMalloc(&h->dValD, h->nblkD * sizeof(double)));
         CK(hipMalloc(&h->dValC, h->nB * sizeof(double)));
@@ -384,11 +409,14 @@ qap_status qap_rlt2_create_ex(int N, const double* F, const double* Dm, const do
     if (h->precision == QAP_FP64) {
         hipLaunchKernelGGL((qap::k_init<double>), dim3(grid_for(h->nC, 256)), dim3(256), 0, h->stream, dF, dDm,
                            dB0, static_cast<double*>(h->dB), static_cast<double*>(h->dC), N);
-        CK(hipGetLastError());
-        // Iteration 0: C -> B, then B -> LB.
-        CK(enqueue_step_any(h, 6));
-        CK(enqueue_step_any(h, 7));
+    } else {
+        hipLaunchKernelGGL((qap::k_init<float>), dim3(grid_for(h->nC, 256)), dim3(256), 0, h->stream, dF, dDm,
+                           dB0, static_cast<float*>(h->dB), static_cast<float*>(h->dC), N);
     }
+    CK(hipGetLastError());
+    // Iteration 0: C -> B, then B -> LB.
+    CK(enqueue_step_any(h, 6));
+    CK(enqueue_step_any(h, 7));
     CK(hipStreamSynchronize(h->stream));
     (void)hipFree(dF);
     (void)hipFree(dDm);
@@ -475,26 +503,12 @@ qap_status qap_rlt2_certify(qap_rlt2* h, double* certified)
     qap_status st = check_handle(h);
     if (st != QAP_OK) return st;
     if (!certified) return fail(QAP_EINVAL, "null output");
-    // Certification cascade on the host copy of the state (FP64).
-    const int N = h->N, n1 = N - 1, n2 = N - 2;
-    std::vector<double> B(h->nB), C(h->nC), D((size_t)h->nblkD * n2 * n2);
-    double lb = 0.0;
-    st = qap_rlt2_read_state(h, &lb, B.data(), C.data(), D.data());
-    if (st != QAP_OK) return st;
-    const int64_t blk = (int64_t)n2 * n2;
-    std::vector<double> ct(h->nC);
-    for (int64_t b = 0; b < h->nblkD; ++b) {
-        double m = 0.0;
-        for (int64_t e = 0; e < blk; ++e) m = std::min(m, D[b * blk + e]);
-        ct[b] = C[b] + (double)n2 * m;
-    }
-    double bmin = 0.0;
-    for (int64_t ij = 0; ij < h->nB; ++ij) {
-        double m = 0.0;
-        for (int64_t e = 0; e < (int64_t)n1 * n1; ++e) m = std::min(m, ct[ij * n1 * n1 + e]);
-        bmin = std::min(bmin, B[ij] + (double)n1 * m);
-    }
-    *certified = lb + (double)N * bmin;
+    hipError_t e = h->precision == QAP_FP64 ? enqueue_certify<double>(h) : enqueue_certify<float>(h);
+    if (e != hipSuccess) return mark_broken(h, e, "certification launch");
+    e = hipMemcpyAsync(certified, h->dCert, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return mark_broken(h, e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return mark_broken(h, e, "hipStreamSynchronize");
     return QAP_OK;
 }
 
@@ -583,13 +597,18 @@ qap_status qap_lap_solve(int batch, const int32_t* n, const int64_t* mat_off, co
     if (batch == 0) return QAP_OK;
     if (!n || !mat_off || !cost || !value) return fail(QAP_EINVAL, "null n, mat_off, cost or value");
     if ((duals || assign) && !vec_off) return fail(QAP_EINVAL, "vec_off needed for duals or assign");
-    if (dtype != QAP_FP64) return fail(QAP_EINVAL, "only FP64 assignment problems are available in this build");
-    const size_t es = sizeof(double);
+    if (dtype != QAP_FP64 && dtype != QAP_FP32_CERTIFIED) return fail(QAP_EINVAL, "unknown dtype");
+    const bool f32 = dtype == QAP_FP32_CERTIFIED;
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int wr = (flags & QAP_LAP_RESIDUAL) ? 1 : 0;
     if (flags & QAP_LAP_DEVICE) {
-        QAP_HIP(launch_batch<double>(st, 64, batch, n, mat_off, vec_off, static_cast<double*>(cost), value,
-                                     static_cast<double*>(duals), assign, wr));
+        if (f32)
+            QAP_HIP(launch_batch<float>(st, 64, batch, n, mat_off, vec_off, static_cast<float*>(cost), value,
+                                        static_cast<float*>(duals), assign, wr));
+        else
+            QAP_HIP(launch_batch<double>(st, 64, batch, n, mat_off, vec_off, static_cast<double*>(cost), value,
+                                         static_cast<double*>(duals), assign, wr));
         return QAP_OK;
     }
     // Host pointers: validate, stage, solve, copy back.
@@ -600,9 +619,11 @@ qap_status qap_lap_solve(int batch, const int32_t* n, const int64_t* mat_off, co
         if (mat_off[b] < 0) return fail(QAP_EINVAL, "negative mat_off");
         maxn = std::max(maxn, (int)n[b]);
         mat_end = std::max(mat_end, mat_off[b] + (int64_t)n[b] * n[b]);
-        const double* cm = static_cast<const double*>(cost) + mat_off[b];
-        for (int64_t e = 0; e < (int64_t)n[b] * n[b]; ++e)
-            if (!std::isfinite(cm[e])) return fail(QAP_EINVAL, "non-finite cost entry");
+        for (int64_t e = 0; e < (int64_t)n[b] * n[b]; ++e) {
+            const double x = f32 ? (double)static_cast<const float*>(cost)[mat_off[b] + e]
+                                 : static_cast<const double*>(cost)[mat_off[b] + e];
+            if (!std::isfinite(x)) return fail(QAP_EINVAL, "non-finite cost entry");
+        }
         if (vec_off) {
             if (vec_off[b] < 0) return fail(QAP_EINVAL, "negative vec_off");
             vec_end = std::max(vec_end, vec_off[b] + (int64_t)n[b]);
@@ -611,7 +632,8 @@ qap_status qap_lap_solve(int batch, const int32_t* n, const int64_t* mat_off, co
     const int seg = seg_for(std::max(maxn, 1));
     int32_t* dn = nullptr;
     int64_t *dmo = nullptr, *dvo = nullptr;
-    double *dcost = nullptr, *dval = nullptr, *ddual = nullptr;
+    void *dcost = nullptr, *ddual = nullptr;
+    double* dval = nullptr;
     int32_t* dassign = nullptr;
     qap_status result = QAP_OK;
     auto cleanup = [&]() {
@@ -641,7 +663,12 @@ qap_status qap_lap_solve(int batch, const int32_t* n, const int64_t* mat_off, co
     }
     if (duals) CK2(hipMalloc(&ddual, std::max<int64_t>(4 * vec_end, 1) * es));
     if (assign) CK2(hipMalloc(&dassign, std::max<int64_t>(vec_end, 1) * sizeof(int32_t)));
-    CK2(launch_batch<double>(st, seg, batch, dn, dmo, dvo, dcost, dval, ddual, dassign, wr));
+    if (f32)
+        CK2(launch_batch<float>(st, seg, batch, dn, dmo, dvo, static_cast<float*>(dcost), dval,
+                                static_cast<float*>(ddual), dassign, wr));
+    else
+        CK2(launch_batch<double>(st, seg, batch, dn, dmo, dvo, static_cast<double*>(dcost), dval,
+                                 static_cast<double*>(ddual), dassign, wr));
     CK2(hipMemcpyAsync(value, dval, batch * sizeof(double), hipMemcpyDeviceToHost, st));
     if (wr) CK2(hipMemcpyAsync(cost, dcost, mat_end * es, hipMemcpyDeviceToHost, st));
     if (duals) CK2(hipMemcpyAsync(duals, ddual, 4 * vec_end * es, hipMemcpyDeviceToHost, st));

@@ -27,6 +27,73 @@ __device__ __forceinline__ int skip2(int r, int lo, int hi) {
 __device__ __forceinline__ int drop1(int x, int a) { return x - (x > a); }
 __device__ __forceinline__ int drop2(int x, int a, int b) { return x - (x > a) - (x > b); }
 
+// ---- arithmetic of the two precisions ---------------------------------------
+// FP64 mode: plain IEEE round-to-nearest; the element-wise steps perform
+// exactly the operations of the algorithm in the same order as a plain
+// sequential reference, and so match it bit for bit.
+//
+// FP32 certified mode: reduced costs are stored as floats, and every value
+// written into the state (B, C, D, LB) is computed in FP64 and rounded
+// toward -inf exactly once.  Rounding down can only lower what the state
+// represents for a permutation, so the represented objective never exceeds
+// the true one and LB stays a valid lower bound.  The directed FP64 steps
+// are built from round-to-nearest operations with their exact errors
+// (TwoSum for sums, the FMA residual for products and quotients), so no
+// hardware rounding mode is changed.
+
+// The next representable value below x (x finite).
+__device__ __forceinline__ double next_down(double x) {
+    if (x == 0.0) return -__longlong_as_double(1ll);
+    const long long b = __double_as_longlong(x);
+    return __longlong_as_double(x > 0.0 ? b - 1 : b + 1);
+}
+__device__ __forceinline__ float next_down(float x) {
+    if (x == 0.0f) return -__int_as_float(1);
+    const int b = __float_as_int(x);
+    return __int_as_float(x > 0.0f ? b - 1 : b + 1);
+}
+// a + b rounded toward -inf.
+__device__ __forceinline__ double add_down(double a, double b) {
+    const double s = a + b;
+    const double bb = s - a;
+    const double err = (a - (s - bb)) + (b - bb);
+    return err < 0.0 ? next_down(s) : s;
+}
+__device__ __forceinline__ double sub_down(double a, double b) { return add_down(a, -b); }
+// a * b rounded toward -inf.
+__device__ __forceinline__ double mul_down(double a, double b) {
+    const double p = a * b;
+    const double err = __builtin_fma(a, b, -p);
+    return err < 0.0 ? next_down(p) : p;
+}
+// a / m rounded toward -inf (m > 0): q*m - a is exact in an FMA.
+__device__ __forceinline__ double div_down(double a, double m) {
+    const double q = a / m;
+    const double r = __builtin_fma(q, m, -a);
+    return r > 0.0 ? next_down(q) : q;
+}
+// Largest float <= x.
+__device__ __forceinline__ float to_float_down(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = next_down(f);
+    return f;
+}
+__device__ __forceinline__ float mul_down_to_float(double a, double b) {
+    const double p = a * b;
+    const double err = __builtin_fma(a, b, -p);
+    float f = (float)p;
+    if ((double)f > p || ((double)f == p && err < 0.0)) f = next_down(f);
+    return f;
+}
+__device__ __forceinline__ float add_down_to_float(double a, double b) {
+    const double s = a + b;
+    const double bb = s - a;
+    const double err = (a - (s - bb)) + (b - bb);
+    float f = (float)s;
+    if ((double)f > s || ((double)f == s && err < 0.0)) f = next_down(f);
+    return f;
+}
+
 // Block number of D_{(a,la),(b,lb)} (= position of c_{a la b lb} in C).
 __device__ __forceinline__ int64_t beta_of(int N, int a, int la, int b, int lb) {
     const int n1 = N - 1;
@@ -49,16 +116,24 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ F, cons
     const int64_t nC = (int64_t)N * N * n1 * n1;
     if (x < (int64_t)N * N) {
         const int i = (int)(x / N), j = (int)(x % N);
-        double b = F[i * N + i] * Dm[j * N + j];
-        if (B0) b = b + B0[x];
-        B[x] = (T)b;
+        if constexpr (sizeof(T) == 8) {
+            double b = F[i * N + i] * Dm[j * N + j];
+            if (B0) b = b + B0[x];
+            B[x] = b;
+        } else {
+            const double b = mul_down(F[i * N + i], Dm[j * N + j]);
+            B[x] = add_down_to_float(b, B0 ? B0[x] : 0.0);
+        }
     }
     if (x < nC) {
         const int ij = (int)(x / (n1 * n1));
         const int rem = (int)(x % (n1 * n1));
         const int i = ij / N, j = ij % N;
         const int k = skip1(rem / n1, i), n = skip1(rem % n1, j);
-        C[x] = (T)(F[i * N + k] * Dm[j * N + n]);
+        if constexpr (sizeof(T) == 8)
+            C[x] = F[i * N + k] * Dm[j * N + n];
+        else
+            C[x] = mul_down_to_float(F[i * N + k], Dm[j * N + n]);
     }
 }
 
@@ -73,9 +148,14 @@ __global__ __launch_bounds__(256) void k_spread_prep(T* __restrict__ C, const T*
     const int n1 = N - 1;
     if (x >= (int64_t)N * N * n1 * n1) return;
     const int ij = (int)(x / (n1 * n1));
-    const T share_b = B[ij] / (T)(N - 1);
-    const T c = C[x] + share_b;
-    CC[x] = c / (T)(N - 2);
+    if constexpr (sizeof(T) == 8) {
+        const T share_b = B[ij] / (T)(N - 1);
+        const T c = C[x] + share_b;
+        CC[x] = c / (T)(N - 2);
+    } else {
+        const double c = add_down((double)C[x], div_down((double)B[ij], (double)(N - 1)));
+        CC[x] = to_float_down(div_down(c, (double)(N - 2)));
+    }
     C[x] = (T)0;
 }
 
@@ -88,18 +168,28 @@ __global__ __launch_bounds__(256) void k_spread_prep(T* __restrict__ C, const T*
 // read and written contiguously.  With P1=(i,j), P2=(k,n), P3=(p,q) the six
 // members are summed in lexicographic order of the permutation of
 // (P1, P2, P3), so the result is the same bits on every run.
+//
+// XCD-aware schedule: the hardware hands workgroup b to XCD b mod 8, and each
+// XCD has its own L2.  All W workgroups of facility triple t are given ids
+// congruent to t mod 8 and consecutive among that XCD's ids, so one XCD works
+// through a triple's six sub-arrays (6 N(N-1)(N-2) entries) together and the
+// partially used cache lines of the four strided members meet in its L2.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __restrict__ CC,
                                                T* __restrict__ B, const int* __restrict__ tri,
-                                               int N, int64_t ldD, int64_t ngroups)
+                                               int N, int64_t ldD, int ntri, int wg_per_tri)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < (int64_t)N * N) B[g] = (T)0;
-    if (g >= ngroups) return;
+    if (blockIdx.x == 0)
+        for (int x = threadIdx.x; x < N * N; x += blockDim.x) B[x] = (T)0;
+    const int xcd = blockIdx.x & 7;
+    const int local = blockIdx.x >> 3;
+    const int t = (local / wg_per_tri) * 8 + xcd;
+    const int w = local % wg_per_tri;
+    if (t >= ntri) return;
     const int n1 = N - 1, n2 = N - 2;
-    const int64_t L = (int64_t)N * n1 * n2;
-    const int t = (int)(g / L);
-    const int loc = (int)(g % L);
+    const int L = N * n1 * n2;
+    const int loc = w * 256 + (int)threadIdx.x;
+    if (loc >= L) return;
     const int qq = loc % n2;
     const int rest = loc / n2;
     const int j = rest / n1;
@@ -117,19 +207,35 @@ __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __re
     const int64_t a4 = b4 * ldD + entry_of(N, p, q, i, j, k, n);
     const int64_t a5 = b5 * ldD + entry_of(N, p, q, k, n, i, j);
 
-    const T m0 = Dd[a0] + CC[b0];
-    const T m1 = Dd[a1] + CC[b1];
-    const T m2 = Dd[a2] + CC[b2];
-    const T m3 = Dd[a3] + CC[b3];
-    const T m4 = Dd[a4] + CC[b4];
-    const T m5 = Dd[a5] + CC[b5];
-    T s = m0;
-    s += m1;
-    s += m2;
-    s += m3;
-    s += m4;
-    s += m5;
-    const T mean = s / (T)6;
+    T mean;
+    if constexpr (sizeof(T) == 8) {
+        const T m0 = Dd[a0] + CC[b0];
+        const T m1 = Dd[a1] + CC[b1];
+        const T m2 = Dd[a2] + CC[b2];
+        const T m3 = Dd[a3] + CC[b3];
+        const T m4 = Dd[a4] + CC[b4];
+        const T m5 = Dd[a5] + CC[b5];
+        T s = m0;
+        s += m1;
+        s += m2;
+        s += m3;
+        s += m4;
+        s += m5;
+        mean = s / (T)6;
+    } else {
+        double s = add_down((double)Dd[a0], (double)CC[b0]);
+        s = add_down(s, (double)Dd[a1]);
+        s = add_down(s, (double)CC[b1]);
+        s = add_down(s, (double)Dd[a2]);
+        s = add_down(s, (double)CC[b2]);
+        s = add_down(s, (double)Dd[a3]);
+        s = add_down(s, (double)CC[b3]);
+        s = add_down(s, (double)Dd[a4]);
+        s = add_down(s, (double)CC[b4]);
+        s = add_down(s, (double)Dd[a5]);
+        s = add_down(s, (double)CC[b5]);
+        mean = to_float_down(div_down(s, 6.0));
+    }
     Dd[a0] = mean;
     Dd[a1] = mean;
     Dd[a2] = mean;
@@ -152,9 +258,61 @@ __global__ __launch_bounds__(256) void k_transfer_C(T* __restrict__ C, int N)
     const int k = skip1(rem / n1, i), n = skip1(rem % n1, j);
     if (i >= k) return;
     const int64_t y = beta_of(N, k, n, i, j);
-    const T mean = (C[x] + C[y]) / (T)2;
+    T mean;
+    if constexpr (sizeof(T) == 8)
+        mean = (C[x] + C[y]) / (T)2;
+    else
+        mean = to_float_down(div_down(add_down((double)C[x], (double)C[y]), 2.0));
     C[x] = mean;
     C[y] = mean;
+}
+
+// ---- FP64 certification cascade (every rounding toward -inf) ----------------
+// For every permutation pi the stored state represents the objective
+//   LB + sum_i b_{i pi(i)} + sum_{i!=k} c_{i pi(i) k pi(k)} + sum d_{...}.
+// With m(beta) = min(0, min of block D_beta):  c~ = c + (N-2) m(beta) bounds
+// the c term plus its block's N-2 entries on pi from below; likewise
+// b~ = b + (N-1) min(0, min of C~_ij), and LB + N min(0, min b~) bounds the
+// whole sum from below whatever the signs of the stored entries.
+
+// One wave per D block: ct[beta] = c_beta + (N-2) * min(0, min D_beta).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cert_D(const T* __restrict__ Dd, int64_t ldD, int blk,
+                                                int64_t nblk, const T* __restrict__ C,
+                                                double* __restrict__ ct, int N)
+{
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= nblk) return;
+    double m = 0.0;
+    for (int e = lane; e < blk; e += 64) m = __builtin_fmin(m, (double)Dd[b * ldD + e]);
+    for (int off = 32; off > 0; off >>= 1) m = __builtin_fmin(m, __shfl_xor(m, off, 64));
+    if (lane == 0) ct[b] = add_down((double)C[b], mul_down((double)(N - 2), m));
+}
+
+// One wave per C block: bt[ij] = b_ij + (N-1) * min(0, min C~_ij).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cert_C(const double* __restrict__ ct, const T* __restrict__ B,
+                                                double* __restrict__ bt, int N)
+{
+    const int ij = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (ij >= N * N) return;
+    const int blk = (N - 1) * (N - 1);
+    double m = 0.0;
+    for (int e = lane; e < blk; e += 64) m = __builtin_fmin(m, ct[(int64_t)ij * blk + e]);
+    for (int off = 32; off > 0; off >>= 1) m = __builtin_fmin(m, __shfl_xor(m, off, 64));
+    if (lane == 0) bt[ij] = add_down((double)B[ij], mul_down((double)(N - 1), m));
+}
+
+// One wave: out = LB + N * min(0, min bt).
+__global__ __launch_bounds__(64) void k_cert_final(const double* __restrict__ bt, int N,
+                                                   const double* __restrict__ lb, double* __restrict__ out)
+{
+    double m = 0.0;
+    for (int e = threadIdx.x; e < N * N; e += 64) m = __builtin_fmin(m, bt[e]);
+    for (int off = 32; off > 0; off >>= 1) m = __builtin_fmin(m, __shfl_xor(m, off, 64));
+    if (threadIdx.x == 0) out[0] = add_down(lb[0], mul_down((double)N, m));
 }
 
 }  // namespace qap
