@@ -147,6 +147,53 @@ qap_status qap_rlt2_read_state(qap_rlt2* h, double* lb, double* B, double* C, do
 /* Release the handle and all of its device memory.  NULL-safe. */
 void qap_rlt2_destroy(qap_rlt2* h);
 
+/* ---- many instances in one handle (branch-and-bound nodes) ------------------
+ * Section 6 of the paper runs the dual ascent at every node of a
+ * branch-and-bound tree; a node is a smaller QAP with linear costs and a
+ * constant (see qap_subproblem).  A batch handle holds `count` independent
+ * instances of possibly different sizes and advances all of them together:
+ * every step of an iteration is one launch over all instances (one per
+ * segment-size class for the concentration steps), and qap_rlt2_ascend
+ * replays one HIP graph per iteration.  Every call above applies to all
+ * instances; the calls that return one instance's data (bound, trace,
+ * lap_values, read_state) return instance 0's.
+ *
+ * qap_rlt2_batch_create: N[k], F[k], D[k] as for qap_rlt2_create_ex; B0
+ * (nullable, or with nullable entries) and constant (nullable: all 0) per
+ * instance.  Each instance runs its own iteration 0. */
+qap_status qap_rlt2_batch_create(int count, const int32_t* N, const double* const* F,
+                                 const double* const* D, const double* const* B0,
+                                 const double* constant, const qap_rlt2_opts* opts,
+                                 qap_rlt2** out);
+
+/* Number of instances in the handle. */
+qap_status qap_rlt2_count(qap_rlt2* h, int* count);
+
+/* Per-instance LB (count entries, nullable) and certified bound (nullable;
+ * the FP64 cascade of qap_rlt2_certify, per instance). */
+qap_status qap_rlt2_batch_bounds(qap_rlt2* h, double* lb, double* certified);
+
+/* Instance k's versions of qap_rlt2_trace, qap_rlt2_lap_values and
+ * qap_rlt2_read_state (sizes follow instance k's N). */
+qap_status qap_rlt2_instance_trace(qap_rlt2* h, int k, int64_t capacity, int64_t* count,
+                                   double* lb, double* lbprime);
+qap_status qap_rlt2_instance_lap_values(qap_rlt2* h, int k, double* sD, double* sC, double* sB);
+qap_status qap_rlt2_instance_state(qap_rlt2* h, int k, double* lb, double* B, double* C, double* D);
+
+/* Branch-and-bound node of a QAP (Section 6): fix facility fac[t] at location
+ * loc[t] for t < m (distinct facilities, distinct locations).  The remaining
+ * free facilities and locations, in ascending order, form a QAP of size
+ * M = N - m with flows Fsub (M x M), distances Dsub (M x M), linear costs
+ *   B0sub[a][b] = sum_t f(i, fac_t) d(j, loc_t) + f(fac_t, i) d(loc_t, j)
+ * for free facility i = a-th and free location j = b-th, and
+ *   *constant = sum_{t,u} f(fac_t, fac_u) d(loc_t, loc_u),
+ * so that the parent's objective of any completion equals *constant plus the
+ * node's objective with linear costs B0sub.  Host memory, FP64; the caller
+ * owns all buffers.  Errors: QAP_EINVAL for bad indices or NULL pointers. */
+qap_status qap_subproblem(int N, const double* F, const double* D, int m, const int32_t* fac,
+                          const int32_t* loc, double* Fsub, double* Dsub, double* B0sub,
+                          double* constant);
+
 /* Batched linear assignment with canonical dual (Section 4.1, the operation
  * behind every cost concentration).
  *

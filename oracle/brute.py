@@ -107,3 +107,24 @@ def represented_objective(lb, B, C, Dd, perm):
     mask3 = (I3 != K3) & (I3 != P3) & (K3 != P3)
     total += float(Dd[I3, perm[I3], K3, perm[K3], P3, perm[P3]][mask3].sum())
     return total
+
+
+def node_instance(F, D, fac, loc):
+    """Branch-and-bound node of a QAP with facility fac[t] fixed at location
+    loc[t]: returns (F', D', B0', constant) over the free facilities and
+    locations in ascending order, written from the objective
+    sum_{i,k} f_ik d_{pi(i) pi(k)} split into free-free, free-fixed (both
+    directions, a linear cost) and fixed-fixed (a constant) terms."""
+    F = np.asarray(F, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    N = F.shape[0]
+    fac = list(int(a) for a in fac)
+    loc = list(int(b) for b in loc)
+    free_f = [i for i in range(N) if i not in fac]
+    free_l = [j for j in range(N) if j not in loc]
+    Fp = F[np.ix_(free_f, free_f)]
+    Dp = D[np.ix_(free_l, free_l)]
+    B0 = (F[np.ix_(free_f, fac)] @ D[np.ix_(free_l, loc)].T
+          + F[np.ix_(fac, free_f)].T @ D[np.ix_(loc, free_l)])
+    const = float((F[np.ix_(fac, fac)] * D[np.ix_(loc, loc)]).sum())
+    return Fp, Dp, B0, const

@@ -5,4 +5,4 @@ The compute path is the HIP library libqap_rlt2.so (C ABI in
 include/qap_rlt2.h); this package is its thin Python binding.
 """
 from ._binding import (MAX_N, QAP_FP32_CERTIFIED, QAP_FP64, QapError, Rlt2, lap_solve,  # noqa: F401
-                       lap_solve_device, lib, LIB_PATH)
+                       lap_solve_device, lib, LIB_PATH, subproblem)

@@ -45,6 +45,14 @@ SIGNATURES = {
     "qap_lap_solve": (ctypes.c_int, [ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp,
                                      ctypes.c_int, _vp]),
     "qap_last_error": (ctypes.c_char_p, []),
+    "qap_rlt2_batch_create": (ctypes.c_int, [ctypes.c_int, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(Opts),
+                                             ctypes.POINTER(_vp)]),
+    "qap_rlt2_count": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    "qap_rlt2_batch_bounds": (ctypes.c_int, [_vp, _dp, _dp]),
+    "qap_rlt2_instance_trace": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int64, _i64p, _dp, _dp]),
+    "qap_rlt2_instance_lap_values": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp, _dp]),
+    "qap_rlt2_instance_state": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp, _dp, _dp]),
+    "qap_subproblem": (ctypes.c_int, [ctypes.c_int, _dp, _dp, ctypes.c_int, _vp, _vp, _dp, _dp, _dp, _dp]),
 }
 
 _lib = None
@@ -94,8 +102,21 @@ def _dptr(a):
     return None if a is None else a.ctypes.data_as(_dp)
 
 
+def _opts(precision, trace_level, use_graph, device, stream):
+    opts = Opts()
+    _check(lib().qap_rlt2_default_opts(ctypes.byref(opts)), "qap_rlt2_default_opts")
+    opts.precision = {"fp64": QAP_FP64, "fp32": QAP_FP32_CERTIFIED}[precision]
+    opts.device = device
+    opts.stream = stream
+    opts.trace_level = trace_level
+    opts.use_graph = 1 if use_graph else 0
+    return opts
+
+
 class Rlt2:
-    """One RLT2 dual-ascent state on the GPU (qap_rlt2_* calls)."""
+    """One RLT2 dual-ascent state on the GPU (qap_rlt2_* calls).  A handle
+    made by Rlt2.batch holds several instances; the plain accessors then
+    refer to instance 0 and the *_k accessors to instance k."""
 
     def __init__(self, F, D, B0=None, constant=0.0, precision="fp64", trace_level=1,
                  use_graph=True, device=-1, stream=None):
@@ -106,19 +127,81 @@ class Rlt2:
         if F.shape != (N, N) or D.shape != (N, N):
             raise ValueError("F and D must be square and of the same size")
         B0 = None if B0 is None else _f64(B0)
-        opts = Opts()
-        _check(L.qap_rlt2_default_opts(ctypes.byref(opts)), "qap_rlt2_default_opts")
-        opts.precision = {"fp64": QAP_FP64, "fp32": QAP_FP32_CERTIFIED}[precision]
-        opts.device = device
-        opts.stream = stream
-        opts.trace_level = trace_level
-        opts.use_graph = 1 if use_graph else 0
+        opts = _opts(precision, trace_level, use_graph, device, stream)
         h = _vp()
         _check(L.qap_rlt2_create_ex(N, _dptr(F), _dptr(D), _dptr(B0), float(constant),
                                     ctypes.byref(opts), ctypes.byref(h)), "qap_rlt2_create_ex")
         self._h = h
         self.N = N
+        self.Ns = [N]
         self.precision = precision
+
+    @classmethod
+    def batch(cls, Fs, Ds, B0s=None, constants=None, precision="fp64", trace_level=1,
+              use_graph=True, device=-1, stream=None):
+        """Many instances (e.g. branch-and-bound nodes) in one handle."""
+        K = len(Fs)
+        Fs = [_f64(F) for F in Fs]
+        Ds = [_f64(D) for D in Ds]
+        Ns = np.array([F.shape[0] for F in Fs], dtype=np.int32)
+        B0s = [None if B is None else _f64(B) for B in (B0s or [None] * K)]
+        consts = np.array(constants if constants is not None else [0.0] * K, dtype=np.float64)
+        fp = (ctypes.c_void_p * K)(*[F.ctypes.data for F in Fs])
+        dp = (ctypes.c_void_p * K)(*[D.ctypes.data for D in Ds])
+        bp = (ctypes.c_void_p * K)(*[None if B is None else B.ctypes.data for B in B0s])
+        opts = _opts(precision, trace_level, use_graph, device, stream)
+        h = _vp()
+        _check(lib().qap_rlt2_batch_create(K, Ns.ctypes.data, ctypes.cast(fp, _vp), ctypes.cast(dp, _vp),
+                                           ctypes.cast(bp, _vp), consts.ctypes.data, ctypes.byref(opts),
+                                           ctypes.byref(h)), "qap_rlt2_batch_create")
+        self = cls.__new__(cls)
+        self._h = h
+        self.N = int(Ns[0])
+        self.Ns = [int(n) for n in Ns]
+        self.precision = precision
+        self._keep = (Fs, Ds, B0s)
+        return self
+
+    def count(self):
+        c = ctypes.c_int()
+        _check(lib().qap_rlt2_count(self._h, ctypes.byref(c)), "qap_rlt2_count")
+        return c.value
+
+    def bounds(self, certified=False):
+        """Per-instance LB (and certified bounds when certified=True)."""
+        K = len(self.Ns)
+        lb = np.empty(K)
+        cert = np.empty(K) if certified else None
+        _check(lib().qap_rlt2_batch_bounds(self._h, _dptr(lb), _dptr(cert)), "qap_rlt2_batch_bounds")
+        return (lb, cert) if certified else lb
+
+    def trace_k(self, k):
+        cnt = ctypes.c_int64()
+        _check(lib().qap_rlt2_instance_trace(self._h, k, 0, ctypes.byref(cnt), None, None), "qap_rlt2_instance_trace")
+        lb = np.empty(cnt.value)
+        lbp = np.empty(cnt.value)
+        _check(lib().qap_rlt2_instance_trace(self._h, k, cnt.value, ctypes.byref(cnt), _dptr(lb), _dptr(lbp)),
+               "qap_rlt2_instance_trace")
+        return lb, lbp
+
+    def lap_values_k(self, k):
+        N = self.Ns[k]
+        sD = np.empty(N * N * (N - 1) * (N - 1))
+        sC = np.empty(N * N)
+        sB = np.empty(1)
+        _check(lib().qap_rlt2_instance_lap_values(self._h, k, _dptr(sD), _dptr(sC), _dptr(sB)),
+               "qap_rlt2_instance_lap_values")
+        return sD, sC, float(sB[0])
+
+    def read_state_k(self, k, want_D=True):
+        N = self.Ns[k]
+        B = np.empty(N * N)
+        C = np.empty(N * N * (N - 1) ** 2)
+        D = np.empty(N * N * (N - 1) ** 2 * (N - 2) ** 2) if want_D else None
+        lb = np.empty(1)
+        _check(lib().qap_rlt2_instance_state(self._h, k, _dptr(lb), _dptr(B), _dptr(C), _dptr(D)),
+               "qap_rlt2_instance_state")
+        return float(lb[0]), B, C, D
 
     def close(self):
         if getattr(self, "_h", None):
@@ -182,6 +265,25 @@ class Rlt2:
         _check(lib().qap_rlt2_read_state(self._h, _dptr(lb), _dptr(B), _dptr(C), _dptr(D)),
                "qap_rlt2_read_state")
         return float(lb[0]), B, C, D
+
+
+def subproblem(F, D, fac, loc):
+    """Branch-and-bound node: fix facility fac[t] at location loc[t].
+    Returns (Fsub, Dsub, B0sub, constant) (qap_subproblem)."""
+    F = _f64(F)
+    D = _f64(D)
+    N = F.shape[0]
+    fac = np.ascontiguousarray(fac, dtype=np.int32)
+    loc = np.ascontiguousarray(loc, dtype=np.int32)
+    m = len(fac)
+    M = N - m
+    Fs = np.empty((M, M))
+    Ds = np.empty((M, M))
+    Bs = np.empty((M, M))
+    c = ctypes.c_double()
+    _check(lib().qap_subproblem(N, _dptr(F), _dptr(D), m, fac.ctypes.data, loc.ctypes.data, _dptr(Fs),
+                                _dptr(Ds), _dptr(Bs), ctypes.byref(c)), "qap_subproblem")
+    return Fs, Ds, Bs, c.value
 
 
 def lap_solve(mats, residual=False, want_duals=True, want_assign=True):

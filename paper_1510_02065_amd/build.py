@@ -3,6 +3,8 @@
 hipcc cross-compiles the device code without a GPU.  Flags:
   -ffp-contract=off   no fused multiply-add contraction, so the element-wise
                       kernels perform exactly the IEEE operations written;
+  -fno-honor-nans     (device code only) NaN never occurs in the state, so
+                      min/max need no NaN canonicalisation;
   -packed-fp32-ops    disabled: no packed FP32 instructions are emitted.
 """
 import os
@@ -29,7 +31,8 @@ def hipcc():
 
 def command(out):
     return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-            "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-ffp-contract=off", "-Xarch_device", "-fno-honor-nans",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
             "-o", out] + SOURCES
 

@@ -1,86 +1,109 @@
-// Cost-concentration kernels (Section 4.1 of arXiv 1510.02065): one wave per
-// workgroup, 64/SEG assignment problems per wave, each staged in LDS.
+// Cost-concentration kernels (Section 4.1 of arXiv 1510.02065).  Each wave
+// works on 64/SEG assignment problems at once (one per SEG-lane segment), each
+// staged in the wave's own LDS region; a workgroup holds WPB independent
+// waves.  Problems of every instance of a handle are served by one launch per
+// segment-size class.
 #pragma once
 #include "lap_wave.hpp"
 
 namespace qap {
 
-// Family kernel: blocks[b*bstride ...] (n x n, row-major, contiguous) for
-// b < nblocks.  parent[b] += S, the block is replaced by its residual, and
-// values[b] = S when values is not null.  Used for D -> C (n = N-2, parent C)
-// and C -> B (n = N-1, parent B).
+// Problems of a family, for the instances of one segment-size class:
+// cls[0..Kc) are the instance ids and pre[] the prefix sums of their problem
+// counts, so problem x belongs to instance cls[find_seg(pre, Kc, x)].
+struct FamilyClass {
+    const int* cls;
+    const long long* pre;
+    int Kc;
+    long long total;
+};
+
+enum : int { kFamD = 0, kFamC = 1 };
+
+// D -> C (fam kFamD: blocks D_beta of size N-2, parent c_beta) or C -> B
+// (kFamC: blocks C_ij of size N-1, parent b_ij).  parent += S, the block is
+// replaced by its residual, values[...] = S when values is not null (values
+// are packed like the parents).
+template <typename T, int SEG, int WPB, int FAM>
+__global__ __launch_bounds__(64 * WPB) void k_lap_family(T* __restrict__ D, T* __restrict__ C,
+                                                         T* __restrict__ B, const Inst* __restrict__ inst,
+                                                         FamilyClass fc, int nmax,
+                                                         double* __restrict__ values)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int LPW = 64 / SEG;
+    const int wave = threadIdx.x >> 6;
+    const int seg = (threadIdx.x & 63) / SEG;
+    const int lane = threadIdx.x & (SEG - 1);
+    const long long x = ((long long)blockIdx.x * WPB + wave) * LPW + seg;
+    const bool active = x < fc.total;
+    int n = 0;
+    T* blk = nullptr;
+    long long pidx = 0;
+    if (active) {
+        const int kk = find_seg(fc.pre, fc.Kc, x);
+        const Inst I = inst[fc.cls[kk]];
+        const long long b = x - fc.pre[kk];
+        if (FAM == kFamD) {
+            n = I.N - 2;
+            blk = D + I.offD + b * I.ldD;
+            pidx = I.offC + b;
+        } else {
+            n = I.N - 1;
+            blk = C + I.offC + b * (long long)(I.N - 1) * (I.N - 1);
+            pidx = I.offB + b;
+        }
+    }
+    const SegScratch<T, SEG> sc(smem + (wave * LPW + seg) * SegLds<T, SEG>::bytes(nmax), n);
+    for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
+    wave_sync();
+    const double S = lap_concentrate_seg<T, SEG>(sc, n, active ? blk : nullptr, nullptr, nullptr);
+    if (active && lane == 0) {
+        T* parent = (FAM == kFamD) ? C : B;
+        if constexpr (sizeof(T) == 8)
+            parent[pidx] = parent[pidx] + S;
+        else
+            parent[pidx] = to_float_down(add_down((double)parent[pidx], S));
+        if (values) values[pidx] = S;
+    }
+}
+
+// B -> LB' and LB += LB' (steps 7-8), one problem of size N per instance of
+// the class.  lb[2k] = LB, lb[2k+1] = LB' (FP64; in FP32 certified mode the
+// bound accumulates rounding toward -inf).  The instance's trace gets
+// (LB, LB') at position counter[k]++ when below trace_cap.
 template <typename T, int SEG>
-__global__ __launch_bounds__(64) void k_lap_family(T* __restrict__ blocks, int64_t bstride, int n,
-                                                   int64_t nblocks, T* __restrict__ parent,
-                                                   double* __restrict__ values)
+__global__ __launch_bounds__(64) void k_lap_B(T* __restrict__ B, const Inst* __restrict__ inst, FamilyClass fc,
+                                              int nmax, double* __restrict__ lb, double* __restrict__ trace,
+                                              long long* __restrict__ counter, long long trace_cap,
+                                              double* __restrict__ values)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int LPW = 64 / SEG;
     const int seg = threadIdx.x / SEG;
     const int lane = threadIdx.x & (SEG - 1);
-    const int64_t b = (int64_t)blockIdx.x * LPW + seg;
-    const bool active = b < nblocks;
-    const size_t sb = SegLds<T, SEG>::bytes(n);
-    unsigned char* base = smem + seg * sb;
-    T* Ms = reinterpret_cast<T*>(base);
-    const size_t mb = SegLds<T, SEG>::mat_bytes(n);
-    int* sig_s = reinterpret_cast<int*>(base + mb);
-    double* va_s = reinterpret_cast<double*>(base + mb + SEG * sizeof(int));
-    double* vb_s = va_s + SEG;
-
-    T* blk = blocks + (active ? b : 0) * bstride;
-    if (active)
-        for (int e = lane; e < n * n; e += SEG) Ms[e] = blk[e];
-    __syncthreads();
-    const double S = lap_concentrate_seg<T, SEG>(Ms, active ? n : 0, sig_s, va_s, vb_s,
-                                                 active ? blk : nullptr, nullptr, nullptr);
+    const long long x = (long long)blockIdx.x * LPW + seg;
+    const bool active = x < fc.total;
+    const int k = active ? fc.cls[x] : 0;
+    const Inst I = inst[k];
+    const int n = active ? I.N : 0;
+    T* blk = B + I.offB;
+    const SegScratch<T, SEG> sc(smem + seg * SegLds<T, SEG>::bytes(nmax), n);
+    for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
+    wave_sync();
+    const double S = lap_concentrate_seg<T, SEG>(sc, n, active ? blk : nullptr, nullptr, nullptr);
     if (active && lane == 0) {
-        if constexpr (sizeof(T) == 8)
-            parent[b] = parent[b] + S;
-        else
-            parent[b] = to_float_down(add_down((double)parent[b], S));
-        if (values) values[b] = S;
-    }
-}
-
-// B -> LB' (steps 7-8): the single N x N problem over B; LB += LB' in FP64.
-// lb[0] = LB, lb[1] = LB'.  The trace gets (LB, LB') at position
-// (*counter)++ when below trace_cap.
-template <typename T, int SEG>
-__global__ __launch_bounds__(64) void k_lap_B(T* __restrict__ B, int n, double* __restrict__ lb,
-                                              double* __restrict__ trace,
-                                              long long* __restrict__ counter, long long trace_cap,
-                                              double* __restrict__ values)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int seg = threadIdx.x / SEG;
-    const int lane = threadIdx.x & (SEG - 1);
-    const bool active = seg == 0;
-    const size_t sb = SegLds<T, SEG>::bytes(n);
-    unsigned char* base = smem + seg * sb;
-    T* Ms = reinterpret_cast<T*>(base);
-    const size_t mb = SegLds<T, SEG>::mat_bytes(n);
-    int* sig_s = reinterpret_cast<int*>(base + mb);
-    double* va_s = reinterpret_cast<double*>(base + mb + SEG * sizeof(int));
-    double* vb_s = va_s + SEG;
-    if (active)
-        for (int e = lane; e < n * n; e += SEG) Ms[e] = B[e];
-    __syncthreads();
-    const double S = lap_concentrate_seg<T, SEG>(Ms, active ? n : 0, sig_s, va_s, vb_s,
-                                                 active ? B : nullptr, nullptr, nullptr);
-    if (active && lane == 0) {
-        // FP32 certified mode accumulates the bound rounding toward -inf.
-        const double L = (sizeof(T) == 4) ? add_down(lb[0], S) : lb[0] + S;
-        lb[0] = L;
-        lb[1] = S;
-        if (values) values[0] = S;
+        const double L = (sizeof(T) == 4) ? add_down(lb[2 * k], S) : lb[2 * k] + S;
+        lb[2 * k] = L;
+        lb[2 * k + 1] = S;
+        if (values) values[k] = S;
         if (counter) {
-            const long long t = *counter;
+            const long long t = counter[k];
             if (t < trace_cap) {
-                trace[2 * t] = L;
-                trace[2 * t + 1] = S;
+                trace[(k * trace_cap + t) * 2] = L;
+                trace[(k * trace_cap + t) * 2 + 1] = S;
             }
-            *counter = t + 1;
+            counter[k] = t + 1;
         }
     }
 }
@@ -104,21 +127,16 @@ __global__ __launch_bounds__(64) void k_lap_batch(int batch, const int32_t* __re
     int n = (b < batch) ? nv[b] : 0;
     const bool bad = n < 0 || n > SEG;
     if (bad) n = 0;
-    const size_t sb = SegLds<T, SEG>::bytes(SEG);
-    unsigned char* base = smem + seg * sb;
-    T* Ms = reinterpret_cast<T*>(base);
-    const size_t mb = SegLds<T, SEG>::mat_bytes(SEG);
-    int* sig_s = reinterpret_cast<int*>(base + mb);
-    double* va_s = reinterpret_cast<double*>(base + mb + SEG * sizeof(int));
-    double* vb_s = va_s + SEG;
+    const SegScratch<T, SEG> sc(smem + seg * SegLds<T, SEG>::bytes(SEG), SEG);
     T* mat = (b < batch && !bad) ? cost + mat_off[b] : nullptr;
     const int64_t vo = (b < batch && !bad) ? vec_off[b] : 0;
-    for (int e = lane; e < n * n; e += SEG) Ms[e] = mat[e];
-    __syncthreads();
+    for (int e = lane; e < n * n; e += SEG) sc.M[e] = mat[e];
+    wave_sync();
     const double S = lap_concentrate_seg<T, SEG>(
-        Ms, n, sig_s, va_s, vb_s, (write_residual && n > 0) ? mat : nullptr,
+        sc, n, (write_residual && n > 0) ? mat : nullptr,
         (duals && n > 0) ? duals + 4 * vo : nullptr, (assign && n > 0) ? assign + vo : nullptr);
-    if (b < batch && lane == 0) value[b] = bad ? __builtin_nan("") : S;
+    // A quiet NaN written by bit pattern marks a problem that was not solved.
+    if (b < batch && lane == 0) value[b] = bad ? __longlong_as_double(0x7ff8000000000000ll) : S;
 }
 
 }  // namespace qap

@@ -7,9 +7,12 @@
 // matrix sits in LDS; lane j stands for column j and, where noted, for row j.
 // A wave therefore works on 64/SEG problems at once.
 //
-// Solver: the Hungarian method in its shortest-augmenting-path form (Munkres;
-// rows inserted one at a time, Dijkstra over columns on reduced costs).  Each
-// Dijkstra step is one LDS row read per lane plus a segment-wide argmin.
+// Solver: the Hungarian method in its shortest-augmenting-path form (Munkres),
+// started from the Jonker-Volgenant column reduction: v_j is the minimum of
+// column j and each row that is the first minimum of some column is matched to
+// the lowest such column.  The remaining free rows are inserted one at a time
+// by Dijkstra over columns on reduced costs; each Dijkstra step is one LDS row
+// read per lane plus a segment-wide argmin.
 //
 // Residual: the optimal dual is not unique, so the residual is taken under a
 // canonical choice that does not depend on the solver's path:
@@ -22,9 +25,11 @@
 // With the solver's duals (u, v) and assignment sigma, v^c - v is the vector
 // of shortest distances in the column graph whose arc c -> q costs the reduced
 // cost M[sigma^-1(c)][q] - u - v >= 0, starting from label -v_q at every
-// column; one dense Dijkstra pass computes it.  The row point is the same on
-// the row graph.  Both residual halves are >= 0 exactly: the subtracted dual
-// is a row (column) minimum of the already rounded differences.
+// column.  One dense Dijkstra pass over the columns computes it (a
+// Bellman-Ford variant in Jacobi rounds is kept for comparison).  The row point
+// is the same on the row graph.  Both
+// residual halves are >= 0 exactly: the subtracted dual is a row (column)
+// minimum of the already rounded differences.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -86,6 +91,16 @@ __device__ __forceinline__ void swap_pair(double x, double& a, double& b) {
         a = __hiloint2double((int)rh[0], (int)rl[0]);
         b = __hiloint2double((int)rh[1], (int)rl[1]);
     }
+}
+
+// Orders this wave's LDS writes before its later LDS reads by other lanes.
+// A wave's LDS operations execute in order, so only compiler reordering has to
+// be prevented; each wave owns its LDS region, so waves of a workgroup need
+// not wait for each other.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ float tmin(float a, float b) { return __builtin_fminf(a, b); }
@@ -172,7 +187,8 @@ struct Seg {
         Idx r;
 #pragma unroll
         for (int g = 0; g < LPW; ++g) {
-            const unsigned long long sm = (SEG == 64) ? m : ((m >> (g * SEG)) & ((1ull << SEG) - 1ull));
+            unsigned long long sm = m;
+            if constexpr (SEG < 64) sm = (m >> (g * SEG)) & ((1ull << SEG) - 1ull);
             r.s[g] = sm ? (int)__builtin_ctzll(sm) : SEG;
         }
         return r;
@@ -207,83 +223,146 @@ struct Seg {
 };
 
 // Per-segment LDS working set, laid out as
-// [matrix n*n of T | sig: SEG ints | vecA: SEG doubles | vecB: SEG doubles].
+// [matrix n*n of T | sig: SEG ints | aux: SEG ints | vecA: SEG doubles |
+//  vecB: SEG doubles].
 template <typename T, int SEG>
 struct SegLds {
     __host__ __device__ static size_t mat_bytes(int n) {
         return (((size_t)n * n * sizeof(T)) + 15) & ~(size_t)15;
     }
     __host__ __device__ static size_t bytes(int n) {
-        return mat_bytes(n) + SEG * (sizeof(int) + 2 * sizeof(double));
+        return mat_bytes(n) + SEG * (2 * sizeof(int) + 2 * sizeof(double));
     }
 };
 
-// Row-canonical point, lanes = rows: u^r = u + shortest distances in the row
-// graph, whose arc s -> r costs the reduced cost M[r][sigma(s)] - u_r -
-// v_sigma(s) >= 0, from label -u_r at every row (one dense Dijkstra pass).
+// Carves a segment's LDS working set.
 template <typename T, int SEG>
-__device__ __forceinline__ T row_canonical(const T* __restrict__ M, int n, int lane, bool ok, int sig,
-                                           T urow, T v)
+struct SegScratch {
+    T* M;
+    int* sig;
+    int* aux;
+    double* va;
+    double* vb;
+    __device__ SegScratch(unsigned char* base, int n) {
+        const size_t mb = SegLds<T, SEG>::mat_bytes(n);
+        M = reinterpret_cast<T*>(base);
+        sig = reinterpret_cast<int*>(base + mb);
+        aux = sig + SEG;
+        va = reinterpret_cast<double*>(base + mb + 2 * SEG * sizeof(int));
+        vb = va + SEG;
+    }
+};
+
+// Canonical point by dense Dijkstra over the columns (lanes = columns):
+// x_q = shortest distance to column q from label -v_q at every column, over
+// arcs c -> q of reduced cost M[p(c)][q] - u_{p(c)} - v_q >= 0.  Returns x.
+template <typename T, int SEG>
+__device__ __forceinline__ T col_dijkstra(const T* __restrict__ M, int n, int lane, bool ok, int col, int p,
+                                          T ucol, T v)
 {
     using S = Seg<SEG>;
     using Idx = typename S::Idx;
     const T INF = inf_of<T>();
-    T distr = ok ? -urow : INF;
-    bool doner = !ok;
+    T dist = ok ? -v : INF;
+    bool done = !ok;
     for (int s = 0; s < n; ++s) {
-        const T cand = doner ? INF : distr;
+        const T cand = done ? INF : dist;
         const T dmin = S::min(cand);
-        const Idx rs_ = S::first(!doner && cand == dmin);
+        const Idx cs_ = S::first(!done && cand == dmin);
+        const int c = S::mine(cs_);
+        if (c >= n) break;
+        const int r = S::bcast(p, cs_);
+        const T ur = S::bcast(ucol, cs_);
+        if (lane == c) done = true;
+        const T nd = dmin + ((M[r * n + col] - ur) - v);
+        if (!done && nd < dist) dist = nd;
+    }
+    return ok ? dist : (T)0;
+}
+
+// Row counterpart (lanes = rows): arcs s -> r of reduced cost
+// M[r][sigma(s)] - u_r - v_{sigma(s)}, from label -u_r.  Returns y.
+template <typename T, int SEG>
+__device__ __forceinline__ T row_dijkstra(const T* __restrict__ M, int n, int lane, bool ok, int row, int sig,
+                                          T urow, T v)
+{
+    using S = Seg<SEG>;
+    using Idx = typename S::Idx;
+    const T INF = inf_of<T>();
+    T dist = ok ? -urow : INF;
+    bool done = !ok;
+    for (int s = 0; s < n; ++s) {
+        const T cand = done ? INF : dist;
+        const T dmin = S::min(cand);
+        const Idx rs_ = S::first(!done && cand == dmin);
         const int srow = S::mine(rs_);
         if (srow >= n) break;
         const Idx cs = S::at(sig, rs_);
         const int csl = S::mine(cs);
         const T vcs = S::bcast(v, cs);
-        if (lane == srow) doner = true;
-        if (!doner) {
-            const T nd = dmin + ((M[lane * n + csl] - urow) - vcs);
-            if (nd < distr) distr = nd;
-        }
+        if (lane == srow) done = true;
+        const T nd = dmin + ((M[row * n + csl] - urow) - vcs);
+        if (!done && nd < dist) dist = nd;
     }
-    return urow + distr;
+    return ok ? dist : (T)0;
 }
 
-// Solve, canonicalise and write residuals for the n x n matrix M (in LDS).
+// Solve, canonicalise and write residuals for the n x n matrix sc.M (in LDS).
 //   n        problem size for this segment (0 <= n <= SEG; segment-uniform).
-//   M        segment's LDS matrix, row stride n (left unchanged).
-//   sig_s, va_s, vb_s: segment's LDS scratch (SEG entries each).
+//   sc       segment's LDS working set; sc.M (row stride n) is left unchanged.
 //   R        nullable; receives the residual, row stride n (global memory).
 //   duals    nullable; receives [uc | vc | ur | vr] (4n values).
 //   assign   nullable; assign[r] = column of row r in the solver's assignment.
-// Returns S to every lane of the segment.  Must be called by whole waves in
-// uniform control flow (it contains block barriers; launch one wave per
-// workgroup).
-template <typename T, int SEG>
-__device__ __forceinline__ double lap_concentrate_seg(const T* __restrict__ M, int n, int* __restrict__ sig_s,
-                                      double* __restrict__ va_s, double* __restrict__ vb_s,
-                                      T* __restrict__ R, T* __restrict__ duals,
-                                      int32_t* __restrict__ assign)
+// Returns S to every lane of the segment.  Must be called by whole waves
+// (every segment of the wave, possibly with different n).
+enum : int { kCanonDijkstra = 0, kCanonBellmanFord = 1 };
+
+template <typename T, int SEG, int CANON = kCanonDijkstra>
+__device__ __forceinline__ double lap_concentrate_seg(const SegScratch<T, SEG>& sc, int n,
+                                                      T* __restrict__ R, T* __restrict__ duals,
+                                                      int32_t* __restrict__ assign)
 {
     using S = Seg<SEG>;
     using Idx = typename S::Idx;
+    const T* __restrict__ M = sc.M;
     const int lane = S::lane();
     const bool ok = lane < n;
+    const int col = ok ? lane : 0;   // clamped column for lanes beyond n
     const T INF = inf_of<T>();
 
-    // ---- Hungarian method, shortest augmenting paths -----------------------
-    // Column lane j keeps: v (column dual), p (row matched to column j or -1),
-    // ucol (dual of row p).  Inserting row i runs Dijkstra over columns with
-    // absolute tentative distances `dist` (reduced costs are >= 0); duals are
-    // only shifted when the search reaches an unmatched column, by
-    // D* - dist_j for every scanned column j (Jonker-Volgenant form).
-    T v = 0, ucol = 0;
-    int p = -1;
+    // ---- column reduction -------------------------------------------------
+    T v = 0;          // column dual (lane = column)
+    int crow = 0;     // first row attaining the column minimum
+    if (ok) {
+        v = M[lane];
+        for (int r = 1; r < n; ++r) {
+            const T m = M[r * n + lane];
+            if (m < v) {
+                v = m;
+                crow = r;
+            }
+        }
+    }
+    sc.aux[lane] = SEG;
+    wave_sync();
+    if (ok) atomicMin(&sc.aux[crow], lane);
+    wave_sync();
+    // p: row matched to this column (or -1); ucol: that row's dual (0 here).
+    int p = (ok && sc.aux[crow] == lane) ? crow : -1;
+    T ucol = 0;
+
+    // ---- Hungarian method for the rows left free -----------------------------
+    // Inserting free row i runs Dijkstra over columns with absolute tentative
+    // distances `dist` (reduced costs are >= 0); duals are only shifted when
+    // the search reaches an unmatched column, by D* - dist_j for every scanned
+    // column j (Jonker-Volgenant form).
     for (int i = 0; i < n; ++i) {
+        if (sc.aux[i] != SEG) continue;   // row i already matched
         T dist = INF;   // tentative distance from row i to column j
         int way = -1;   // previous column on the shortest path (-1: row i)
         bool used = false;
         int i0 = i;     // row being scanned
-        T ui0 = 0;      // its dual (row i has dual 0 before insertion)
+        T ui0 = 0;      // its dual (a free row has dual 0)
         T d0 = 0;       // distance at which row i0 was reached
         int j0 = -1;    // column through which row i0 was reached
         int jend = -1;
@@ -291,16 +370,15 @@ __device__ __forceinline__ double lap_concentrate_seg(const T* __restrict__ M, i
         // Each pass scans one more column, so a well-formed search ends within
         // n passes; the bound also ends it on non-finite input.
         for (int pass = 0; pass <= n; ++pass) {
-            if (ok && !used) {
-                const T cur = d0 + ((M[i0 * n + lane] - ui0) - v);
-                if (cur < dist) {
-                    dist = cur;
-                    way = j0;
-                }
+            const T cur = d0 + ((M[i0 * n + col] - ui0) - v);
+            const bool live = ok && !used;
+            if (live && cur < dist) {
+                dist = cur;
+                way = j0;
             }
-            const T cand = (ok && !used) ? dist : INF;
+            const T cand = live ? dist : INF;
             const T dmin = S::min(cand);
-            const Idx j1s = S::first(ok && !used && cand == dmin);
+            const Idx j1s = S::first(live && cand == dmin);
             const int j1 = S::mine(j1s);
             if (j1 >= n) break;   // no candidate: non-finite costs
             const int pj = S::bcast(p, j1s);
@@ -338,55 +416,74 @@ __device__ __forceinline__ double lap_concentrate_seg(const T* __restrict__ M, i
         }
     }
 
-    // sigma (column of row r) for lane r, and the solver's row dual u_r.
-    if (ok && p >= 0 && p < n) sig_s[p] = lane;
-    __syncthreads();
-    const int sig = ok ? sig_s[lane] : 0;
+    // sigma (column of row r) for lane r, the solver's row dual u_r and the
+    // dual of the column matched to row r.
+    wave_sync();
+    if (ok && p >= 0 && p < n) sc.sig[p] = lane;
+    sc.aux[lane] = (ok && p >= 0) ? p : 0;
+    wave_sync();
+    const int sig = ok ? sc.sig[lane] : 0;
     const T urow = S::read(ucol, sig);
+    const T vsig = S::read(v, sig);
 
-    // ---- column-canonical point (lanes = columns) ---------------------------
-    T dist = ok ? -v : INF;
-    bool done = !ok;
-    for (int s = 0; s < n; ++s) {
-        const T cand = done ? INF : dist;
-        const T dmin = S::min(cand);
-        const Idx cs_ = S::first(!done && cand == dmin);
-        const int c = S::mine(cs_);
-        if (c >= n) break;
-        const int r = S::bcast(p, cs_);
-        const T ur = S::bcast(ucol, cs_);
-        if (lane == c) done = true;
-        if (!done) {
-            const T nd = dmin + ((M[r * n + lane] - ur) - v);
-            if (nd < dist) dist = nd;
+    // ---- canonical points ------------------------------------------------------
+    T x, y;
+    if constexpr (CANON == kCanonDijkstra) {
+        x = col_dijkstra<T, SEG>(M, n, lane, ok, col, p, ucol, v);
+        y = row_dijkstra<T, SEG>(M, n, lane, ok, col, sig, urow, v);
+    } else {
+        // Bellman-Ford in Jacobi rounds.  Columns:
+        // x_q <- min(x_q, min_c (x_c - u_{p(c)}) + M[p(c)][q] - v_q), from x = -v.
+        x = ok ? -v : (T)0;
+        for (int round = 0; round < SEG; ++round) {
+            sc.va[lane] = ok ? (double)(x - ucol) : 0.0;
+            wave_sync();
+            T best = INF;
+            for (int c = 0; c < n; ++c) best = tmin(best, (T)sc.va[c] + M[sc.aux[c] * n + col]);
+            const T cand = best - v;
+            const bool ch = ok && cand < x;
+            if (ch) x = cand;
+            wave_sync();
+            if (__ballot(ch) == 0ull) break;
+        }
+        // Rows: y_r <- min(y_r, min_s (y_s - v_{sigma(s)}) + M[r][sigma(s)] - u_r), from y = -u.
+        sc.aux[lane] = sig;
+        y = ok ? -urow : (T)0;
+        for (int round = 0; round < SEG; ++round) {
+            sc.vb[lane] = ok ? (double)(y - vsig) : 0.0;
+            wave_sync();
+            T best = INF;
+            for (int s2 = 0; s2 < n; ++s2) best = tmin(best, (T)sc.vb[s2] + M[col * n + sc.aux[s2]]);
+            const T cand = best - urow;
+            const bool ch = ok && cand < y;
+            if (ch) y = cand;
+            wave_sync();
+            if (__ballot(ch) == 0ull) break;
         }
     }
-    const T vc = v + dist;
+    const T vc = v + x;
+    const T ur = urow + y;
+    wave_sync();
 
     if constexpr (sizeof(T) == 8) {
         // ---- FP64: residual = mean of the residuals under the two points ----
-        if (ok) va_s[lane] = vc;
-        __syncthreads();
+        sc.va[lane] = vc;
+        sc.vb[lane] = ur;
+        wave_sync();
         T uc = INF;   // lane as row r
-        if (ok) {
-            for (int q = 0; q < n; ++q) uc = tmin(uc, M[lane * n + q] - (T)va_s[q]);
-        }
-        const T ur = row_canonical<T, SEG>(M, n, lane, ok, sig, urow, v);
-        __syncthreads();
-        if (ok) vb_s[lane] = ur;
-        __syncthreads();
         T vr = INF;   // lane as column q
         if (ok) {
-            for (int r = 0; r < n; ++r) vr = tmin(vr, M[r * n + lane] - (T)vb_s[r]);
+            for (int q = 0; q < n; ++q) uc = tmin(uc, M[lane * n + q] - (T)sc.va[q]);
+            for (int r = 0; r < n; ++r) vr = tmin(vr, M[r * n + lane] - (T)sc.vb[r]);
         }
-        __syncthreads();
-        if (ok) va_s[lane] = uc;
-        __syncthreads();
+        wave_sync();
+        sc.va[lane] = uc;
+        wave_sync();
         if (R != nullptr && ok) {
             for (int r = 0; r < n; ++r) {
                 const T m = M[r * n + lane];
-                const T r1 = (m - vc) - (T)va_s[r];
-                const T r2 = (m - (T)vb_s[r]) - vr;
+                const T r1 = (m - vc) - (T)sc.va[r];
+                const T r2 = (m - (T)sc.vb[r]) - vr;
                 R[r * n + lane] = (T)0.5 * (r1 + r2);
             }
         }
@@ -401,7 +498,7 @@ __device__ __forceinline__ double lap_concentrate_seg(const T* __restrict__ M, i
         const T svc = S::sum(ok ? vc : (T)0);
         const T sur = S::sum(ok ? ur : (T)0);
         const T svr = S::sum(ok ? vr : (T)0);
-        __syncthreads();
+        wave_sync();
         return 0.5 * ((suc + svc) + (sur + svr));
     } else {
         // ---- FP32 certified: the duals are completed in FP64 rounding toward
@@ -409,28 +506,23 @@ __device__ __forceinline__ double lap_concentrate_seg(const T* __restrict__ M, i
         // U = (uc + ur)/2 and V = (vc + vr)/2 the residual M - U - V (the same
         // value as the mean of the two residuals) is then >= 0, and each entry
         // and S = sum U + sum V are rounded down once.
-        if (ok) va_s[lane] = (double)vc;
-        __syncthreads();
+        sc.va[lane] = (double)vc;
+        sc.vb[lane] = (double)ur;
+        wave_sync();
         double uc = __builtin_huge_val();   // lane as row r
-        if (ok) {
-            for (int q = 0; q < n; ++q) uc = __builtin_fmin(uc, sub_down((double)M[lane * n + q], va_s[q]));
-        }
-        const T ur = row_canonical<T, SEG>(M, n, lane, ok, sig, urow, v);
-        __syncthreads();
-        if (ok) vb_s[lane] = (double)ur;
-        __syncthreads();
         double vr = __builtin_huge_val();   // lane as column q
         if (ok) {
-            for (int r = 0; r < n; ++r) vr = __builtin_fmin(vr, sub_down((double)M[r * n + lane], vb_s[r]));
+            for (int q = 0; q < n; ++q) uc = __builtin_fmin(uc, sub_down((double)M[lane * n + q], sc.va[q]));
+            for (int r = 0; r < n; ++r) vr = __builtin_fmin(vr, sub_down((double)M[r * n + lane], sc.vb[r]));
         }
         const double U = ok ? 0.5 * add_down(uc, (double)ur) : 0.0;    // lane as row
         const double V = ok ? 0.5 * add_down((double)vc, vr) : 0.0;    // lane as column
-        __syncthreads();
-        if (ok) va_s[lane] = U;
-        __syncthreads();
+        wave_sync();
+        sc.va[lane] = U;
+        wave_sync();
         if (R != nullptr && ok) {
             for (int r = 0; r < n; ++r)
-                R[r * n + lane] = to_float_down(sub_down(sub_down((double)M[r * n + lane], V), va_s[r]));
+                R[r * n + lane] = to_float_down(sub_down(sub_down((double)M[r * n + lane], V), sc.va[r]));
         }
         if (duals != nullptr && ok) {
             duals[lane] = (T)uc;
@@ -441,7 +533,7 @@ __device__ __forceinline__ double lap_concentrate_seg(const T* __restrict__ M, i
         if (assign != nullptr && ok) assign[lane] = sig;
         const double su = S::sum_down(U);
         const double sv = S::sum_down(V);
-        __syncthreads();
+        wave_sync();
         return add_down(su, sv);
     }
 }

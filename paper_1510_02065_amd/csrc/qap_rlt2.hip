@@ -1,6 +1,6 @@
-// Host side of the qap_rlt2 library: handle state, launch schedule of one
-// dual-ascent iteration (Algorithm 1 of arXiv 1510.02065), HIP-graph replay,
-// and the C ABI declared in include/qap_rlt2.h.
+// Host side of the qap_rlt2 library: handle state for one or many instances,
+// the launch schedule of one dual-ascent iteration (Algorithm 1 of
+// arXiv 1510.02065), HIP-graph replay, and the C ABI of include/qap_rlt2.h.
 #include "qap_rlt2.h"
 
 #include <hip/hip_runtime.h>
@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -41,56 +42,133 @@ int seg_for(int n)
     return 64;
 }
 
-inline unsigned grid_for(int64_t work, int threads) { return (unsigned)((work + threads - 1) / threads); }
+inline unsigned grid_for(long long work, int threads) { return (unsigned)((work + threads - 1) / threads); }
 
-// ---- launch helpers (one wave per workgroup for the assignment kernels) ----
+constexpr long long kTraceCap = 1024;
+
+// Instances of one family that share a segment size.
+struct ClassHost {
+    int seg = 0;
+    int nmax = 0;
+    std::vector<int> ids;
+    std::vector<long long> pre;
+    long long total = 0;
+    int* d_ids = nullptr;
+    long long* d_pre = nullptr;
+    qap::FamilyClass dev() const { return qap::FamilyClass{d_ids, d_pre, (int)ids.size(), total}; }
+};
+
+}  // namespace
+
+// ============================================================================
+// Handle
+// ============================================================================
+
+struct qap_rlt2 {
+    int K = 0;
+    int precision = QAP_FP64;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int trace_level = 1;
+    int use_graph = 1;
+    size_t elem = 8;   // bytes per reduced cost
+    std::vector<qap::Inst> inst;
+    long long totalB = 0, totalC = 0, totalD = 0, totalWG = 0;
+    std::vector<long long> preB, preC, preWG;
+    ClassHost fam[3][4];   // [D, C, B][segment class]
+    qap::Inst* dInst = nullptr;
+    long long *dPreB = nullptr, *dPreC = nullptr, *dPreWG = nullptr;
+    void* dB = nullptr;
+    void* dC = nullptr;
+    void* dD = nullptr;
+    void* dCC = nullptr;
+    double* dLB = nullptr;      // [LB, LB'] per instance
+    double* dValD = nullptr;    // per-block values of the last step 4 (packed like C)
+    double* dValC = nullptr;    // per-block values of the last step 6 (packed like B)
+    double* dValB = nullptr;    // per-instance value of the last step 7
+    double* dTrace = nullptr;   // K x kTraceCap x (LB, LB')
+    long long* dCounter = nullptr;
+    int* dTri = nullptr;
+    double* dCt = nullptr;      // certification: c~ (packed like C)
+    double* dBt = nullptr;      // certification: b~ (packed like B)
+    double* dCert = nullptr;    // certification result per instance
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<std::vector<double>> tLB, tLBp;
+    int64_t iterations = 0;
+    bool broken = false;
+};
+
+namespace {
+
+// ---- launches ---------------------------------------------------------------
 
 template <typename T, int SEG>
-hipError_t launch_family_seg(hipStream_t st, T* blocks, int64_t bstride, int n, int64_t nblocks,
-                             T* parent, double* values)
+hipError_t launch_family_seg(qap_rlt2* h, int famk, const ClassHost& c, double* values)
 {
-    if (nblocks <= 0) return hipSuccess;
+    if (c.total <= 0) return hipSuccess;
     constexpr int LPW = 64 / SEG;
-    const size_t lds = LPW * qap::SegLds<T, SEG>::bytes(n);
-    const unsigned grid = (unsigned)((nblocks + LPW - 1) / LPW);
-    hipLaunchKernelGGL((qap::k_lap_family<T, SEG>), dim3(grid), dim3(64), lds, st, blocks, bstride, n,
-                       nblocks, parent, values);
+    constexpr int WPB = 1;
+    const size_t lds = (size_t)WPB * LPW * qap::SegLds<T, SEG>::bytes(c.nmax);
+    const unsigned grid = (unsigned)((c.total + (long long)WPB * LPW - 1) / ((long long)WPB * LPW));
+    T* D = static_cast<T*>(h->dD);
+    T* C = static_cast<T*>(h->dC);
+    T* B = static_cast<T*>(h->dB);
+    if (famk == qap::kFamD)
+        hipLaunchKernelGGL((qap::k_lap_family<T, SEG, WPB, qap::kFamD>), dim3(grid), dim3(64 * WPB), lds,
+                           h->stream, D, C, B, h->dInst, c.dev(), c.nmax, values);
+    else
+        hipLaunchKernelGGL((qap::k_lap_family<T, SEG, WPB, qap::kFamC>), dim3(grid), dim3(64 * WPB), lds,
+                           h->stream, D, C, B, h->dInst, c.dev(), c.nmax, values);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_family(hipStream_t st, T* blocks, int64_t bstride, int n, int64_t nblocks, T* parent,
-                         double* values)
+hipError_t launch_family(qap_rlt2* h, int famk, double* values)
 {
-    switch (seg_for(n)) {
-    case 8: return launch_family_seg<T, 8>(st, blocks, bstride, n, nblocks, parent, values);
-    case 16: return launch_family_seg<T, 16>(st, blocks, bstride, n, nblocks, parent, values);
-    case 32: return launch_family_seg<T, 32>(st, blocks, bstride, n, nblocks, parent, values);
-    default: return launch_family_seg<T, 64>(st, blocks, bstride, n, nblocks, parent, values);
+    for (const ClassHost& c : h->fam[famk]) {
+        if (c.total <= 0) continue;
+        hipError_t e;
+        switch (c.seg) {
+        case 8: e = launch_family_seg<T, 8>(h, famk, c, values); break;
+        case 16: e = launch_family_seg<T, 16>(h, famk, c, values); break;
+        case 32: e = launch_family_seg<T, 32>(h, famk, c, values); break;
+        default: e = launch_family_seg<T, 64>(h, famk, c, values); break;
+        }
+        if (e != hipSuccess) return e;
     }
+    return hipSuccess;
 }
 
 template <typename T, int SEG>
-hipError_t launch_B_seg(hipStream_t st, T* B, int n, double* lb, double* trace, long long* counter,
-                        long long cap, double* values)
+hipError_t launch_B_seg(qap_rlt2* h, const ClassHost& c)
 {
     constexpr int LPW = 64 / SEG;
-    const size_t lds = LPW * qap::SegLds<T, SEG>::bytes(n);
-    hipLaunchKernelGGL((qap::k_lap_B<T, SEG>), dim3(1), dim3(64), lds, st, B, n, lb, trace, counter, cap,
-                       values);
+    const size_t lds = LPW * qap::SegLds<T, SEG>::bytes(c.nmax);
+    const unsigned grid = (unsigned)((c.total + LPW - 1) / LPW);
+    const bool tr = h->trace_level >= 1;
+    hipLaunchKernelGGL((qap::k_lap_B<T, SEG>), dim3(grid), dim3(64), lds, h->stream, static_cast<T*>(h->dB),
+                       h->dInst, c.dev(), c.nmax, h->dLB, tr ? h->dTrace : nullptr, tr ? h->dCounter : nullptr,
+                       kTraceCap, h->trace_level >= 2 ? h->dValB : nullptr);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_B(hipStream_t st, T* B, int n, double* lb, double* trace, long long* counter,
-                    long long cap, double* values)
+hipError_t launch_B(qap_rlt2* h)
 {
-    switch (seg_for(n)) {
-    case 8: return launch_B_seg<T, 8>(st, B, n, lb, trace, counter, cap, values);
-    case 16: return launch_B_seg<T, 16>(st, B, n, lb, trace, counter, cap, values);
-    case 32: return launch_B_seg<T, 32>(st, B, n, lb, trace, counter, cap, values);
-    default: return launch_B_seg<T, 64>(st, B, n, lb, trace, counter, cap, values);
+    for (const ClassHost& c : h->fam[2]) {
+        if (c.total <= 0) continue;
+        hipError_t e;
+        switch (c.seg) {
+        case 8: e = launch_B_seg<T, 8>(h, c); break;
+        case 16: e = launch_B_seg<T, 16>(h, c); break;
+        case 32: e = launch_B_seg<T, 32>(h, c); break;
+        default: e = launch_B_seg<T, 64>(h, c); break;
+        }
+        if (e != hipSuccess) return e;
     }
+    return hipSuccess;
 }
 
 template <typename T, int SEG>
@@ -118,51 +196,9 @@ hipError_t launch_batch(hipStream_t st, int seg, int batch, const int32_t* n, co
     }
 }
 
-constexpr long long kTraceCap = 1024;
-
-}  // namespace
-
-// ============================================================================
-// Handle
-// ============================================================================
-
-struct qap_rlt2 {
-    int N = 0;
-    int precision = QAP_FP64;
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int trace_level = 1;
-    int use_graph = 1;
-    size_t elem = 8;       // bytes per reduced cost
-    int64_t nB = 0, nC = 0, nblkD = 0, ldD = 0, ngroups = 0;
-    void* dB = nullptr;
-    void* dC = nullptr;
-    void* dD = nullptr;
-    void* dCC = nullptr;
-    double* dLB = nullptr;      // [LB, LB']
-    double* dValD = nullptr;    // per-block values of the last step 4
-    double* dValC = nullptr;    // per-block values of the last step 6
-    double* dValB = nullptr;
-    double* dTrace = nullptr;   // kTraceCap x (LB, LB')
-    long long* dCounter = nullptr;
-    int* dTri = nullptr;
-    double* dCt = nullptr;      // certification: c~ per C entry
-    double* dBt = nullptr;      // certification: b~ per B entry
-    double* dCert = nullptr;    // certification result
-    hipGraphExec_t graph_exec = nullptr;
-    hipGraph_t graph = nullptr;
-    std::vector<double> tLB, tLBp;
-    int64_t iterations = 0;
-    bool broken = false;
-};
-
-namespace {
-
 template <typename T>
 hipError_t enqueue_step(qap_rlt2* h, int step)
 {
-    const int N = h->N;
     T* B = static_cast<T*>(h->dB);
     T* C = static_cast<T*>(h->dC);
     T* D = static_cast<T*>(h->dD);
@@ -171,26 +207,24 @@ hipError_t enqueue_step(qap_rlt2* h, int step)
     const bool vals = h->trace_level >= 2;
     switch (step) {
     case 3: {   // steps 1-3
-        hipLaunchKernelGGL((qap::k_spread_prep<T>), dim3(grid_for(h->nC, 256)), dim3(256), 0, st, C, B, CC, N);
+        hipLaunchKernelGGL((qap::k_spread_prep<T>), dim3(grid_for(h->totalC, 256)), dim3(256), 0, st, C, B, CC,
+                           h->dInst, h->dPreC, h->K, h->totalC);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        const int ntri = N * (N - 1) * (N - 2) / 6;
-        const int wpt = (N * (N - 1) * (N - 2) + 255) / 256;
-        const unsigned grid = (unsigned)(8 * ((ntri + 7) / 8) * wpt);
-        hipLaunchKernelGGL((qap::k_sweep<T>), dim3(grid), dim3(256), 0, st, D, CC, B, h->dTri, N, h->ldD, ntri,
-                           wpt);
+        hipLaunchKernelGGL((qap::k_sweep<T>), dim3((unsigned)h->totalWG), dim3(256), 0, st, D, CC, B, h->dTri,
+                           h->dInst, h->dPreWG, h->K, h->totalB);
         return hipGetLastError();
     }
     case 4:
-        return launch_family<T>(st, D, h->ldD, N - 2, h->nblkD, C, vals ? h->dValD : nullptr);
+        return launch_family<T>(h, qap::kFamD, vals ? h->dValD : nullptr);
     case 5:
-        hipLaunchKernelGGL((qap::k_transfer_C<T>), dim3(grid_for(h->nC, 256)), dim3(256), 0, st, C, N);
+        hipLaunchKernelGGL((qap::k_transfer_C<T>), dim3(grid_for(h->totalC, 256)), dim3(256), 0, st, C, h->dInst,
+                           h->dPreC, h->K, h->totalC);
         return hipGetLastError();
     case 6:
-        return launch_family<T>(st, C, (int64_t)(N - 1) * (N - 1), N - 1, h->nB, B, vals ? h->dValC : nullptr);
+        return launch_family<T>(h, qap::kFamC, vals ? h->dValC : nullptr);
     case 7:
-        return launch_B<T>(st, B, N, h->dLB, h->trace_level >= 1 ? h->dTrace : nullptr,
-                           h->trace_level >= 1 ? h->dCounter : nullptr, kTraceCap, vals ? h->dValB : nullptr);
+        return launch_B<T>(h);
     default:
         return hipErrorInvalidValue;
     }
@@ -199,18 +233,17 @@ hipError_t enqueue_step(qap_rlt2* h, int step)
 template <typename T>
 hipError_t enqueue_certify(qap_rlt2* h)
 {
-    const int N = h->N, n2 = N - 2;
     hipStream_t st = h->stream;
-    hipLaunchKernelGGL((qap::k_cert_D<T>), dim3(grid_for(h->nblkD, 4)), dim3(256), 0, st,
-                       static_cast<const T*>(h->dD), h->ldD, n2 * n2, h->nblkD, static_cast<const T*>(h->dC),
-                       h->dCt, N);
+    hipLaunchKernelGGL((qap::k_cert_D<T>), dim3(grid_for(h->totalC, 4)), dim3(256), 0, st,
+                       static_cast<const T*>(h->dD), static_cast<const T*>(h->dC), h->dCt, h->dInst, h->dPreC,
+                       h->K, h->totalC);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((qap::k_cert_C<T>), dim3(grid_for(h->nB, 4)), dim3(256), 0, st, h->dCt,
-                       static_cast<const T*>(h->dB), h->dBt, N);
+    hipLaunchKernelGGL((qap::k_cert_C<T>), dim3(grid_for(h->totalB, 4)), dim3(256), 0, st, h->dCt,
+                       static_cast<const T*>(h->dB), h->dBt, h->dInst, h->dPreB, h->K, h->totalB);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(qap::k_cert_final, dim3(1), dim3(64), 0, st, h->dBt, N, h->dLB, h->dCert);
+    hipLaunchKernelGGL(qap::k_cert_final, dim3(h->K), dim3(64), 0, st, h->dBt, h->dLB, h->dCert, h->dInst);
     return hipGetLastError();
 }
 
@@ -228,25 +261,29 @@ hipError_t enqueue_iteration(qap_rlt2* h)
     return hipSuccess;
 }
 
-// Copy the trace entries written since the counter was last reset, then reset.
+// Copy the trace entries written since the counters were last reset, then
+// reset them.
 qap_status drain_trace(qap_rlt2* h)
 {
-    long long cnt = 0;
-    QAP_HIP(hipMemcpyAsync(&cnt, h->dCounter, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    std::vector<long long> cnt(h->K);
+    QAP_HIP(hipMemcpyAsync(cnt.data(), h->dCounter, h->K * sizeof(long long), hipMemcpyDeviceToHost, h->stream));
     QAP_HIP(hipStreamSynchronize(h->stream));
-    cnt = std::min(cnt, kTraceCap);
-    if (cnt > 0) {
-        std::vector<double> buf(2 * (size_t)cnt);
+    long long mx = 0;
+    for (long long c : cnt) mx = std::max(mx, std::min(c, kTraceCap));
+    if (mx > 0) {
+        std::vector<double> buf((size_t)h->K * kTraceCap * 2);
         QAP_HIP(hipMemcpyAsync(buf.data(), h->dTrace, buf.size() * sizeof(double), hipMemcpyDeviceToHost,
                                h->stream));
         QAP_HIP(hipStreamSynchronize(h->stream));
-        for (long long t = 0; t < cnt; ++t) {
-            h->tLB.push_back(buf[2 * t]);
-            h->tLBp.push_back(buf[2 * t + 1]);
+        for (int k = 0; k < h->K; ++k) {
+            const long long c = std::min(cnt[k], kTraceCap);
+            for (long long t = 0; t < c; ++t) {
+                h->tLB[k].push_back(buf[((size_t)k * kTraceCap + t) * 2]);
+                h->tLBp[k].push_back(buf[((size_t)k * kTraceCap + t) * 2 + 1]);
+            }
         }
     }
-    const long long zero = 0;
-    QAP_HIP(hipMemcpyAsync(h->dCounter, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
+    QAP_HIP(hipMemsetAsync(h->dCounter, 0, h->K * sizeof(long long), h->stream));
     QAP_HIP(hipStreamSynchronize(h->stream));
     return QAP_OK;
 }
@@ -256,10 +293,16 @@ void release(qap_rlt2* h)
     if (!h) return;
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
-    void* ptrs[] = {h->dB, h->dC, h->dD, h->dCC, h->dLB, h->dValD, h->dValC, h->dValB, h->dTrace,
-                    h->dCounter, h->dTri, h->dCt, h->dBt, h->dCert};
+    void* ptrs[] = {h->dB,     h->dC,     h->dD,     h->dCC,   h->dLB,       h->dValD, h->dValC,
+                    h->dValB,  h->dTrace, h->dCounter, h->dTri, h->dCt,    h->dBt,   h->dCert,
+                    h->dInst,  h->dPreB,  h->dPreC,  h->dPreWG};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    for (auto& f : h->fam)
+        for (auto& c : f) {
+            if (c.d_ids) (void)hipFree(c.d_ids);
+            if (c.d_pre) (void)hipFree(c.d_pre);
+        }
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
 
@@ -276,6 +319,15 @@ qap_status mark_broken(qap_rlt2* h, hipError_t e, const char* what)
 {
     h->broken = true;
     return fail(QAP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename X>
+hipError_t upload(X** dst, const std::vector<X>& v, hipStream_t st)
+{
+    hipError_t e = hipMalloc(dst, std::max<size_t>(v.size(), 1) * sizeof(X));
+    if (e != hipSuccess) return e;
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, st);
 }
 
 }  // namespace
@@ -301,15 +353,32 @@ qap_status qap_rlt2_create(int N, const double* F, const double* D, qap_rlt2** o
 qap_status qap_rlt2_create_ex(int N, const double* F, const double* Dm, const double* B0, double constant,
                               const qap_rlt2_opts* opts, qap_rlt2** out)
 {
+    const int32_t n32 = N;
+    const double* Fs[1] = {F};
+    const double* Ds[1] = {Dm};
+    const double* Bs[1] = {B0};
+    return qap_rlt2_batch_create(1, &n32, Fs, Ds, Bs, &constant, opts, out);
+}
+
+qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* const* Fs, const double* const* Ds,
+                                 const double* const* B0s, const double* constants, const qap_rlt2_opts* opts,
+                                 qap_rlt2** out)
+{
     g_last_error.clear();
     if (!out) return fail(QAP_EINVAL, "null output handle pointer");
     *out = nullptr;
-    if (N < 3 || N > QAP_RLT2_MAX_N) return fail(QAP_EINVAL, "N must be in [3, 64]");
-    if (!F || !Dm) return fail(QAP_EINVAL, "null F or D");
-    for (int x = 0; x < N * N; ++x)
-        if (!std::isfinite(F[x]) || !std::isfinite(Dm[x]) || (B0 && !std::isfinite(B0[x])))
-            return fail(QAP_EINVAL, "non-finite entry in F, D or B0");
-    if (!std::isfinite(constant)) return fail(QAP_EINVAL, "non-finite constant");
+    if (count < 1) return fail(QAP_EINVAL, "count must be >= 1");
+    if (!Ns || !Fs || !Ds) return fail(QAP_EINVAL, "null N, F or D array");
+    for (int k = 0; k < count; ++k) {
+        const int N = Ns[k];
+        if (N < 3 || N > QAP_RLT2_MAX_N) return fail(QAP_EINVAL, "N must be in [3, 64]");
+        if (!Fs[k] || !Ds[k]) return fail(QAP_EINVAL, "null F or D");
+        const double* B0 = B0s ? B0s[k] : nullptr;
+        for (int x = 0; x < N * N; ++x)
+            if (!std::isfinite(Fs[k][x]) || !std::isfinite(Ds[k][x]) || (B0 && !std::isfinite(B0[x])))
+                return fail(QAP_EINVAL, "non-finite entry in F, D or B0");
+        if (constants && !std::isfinite(constants[k])) return fail(QAP_EINVAL, "non-finite constant");
+    }
     qap_rlt2_opts o;
     qap_rlt2_default_opts(&o);
     if (opts) o = *opts;
@@ -318,11 +387,13 @@ qap_status qap_rlt2_create_ex(int N, const double* F, const double* Dm, const do
 
     qap_rlt2* h = new (std::nothrow) qap_rlt2();
     if (!h) return fail(QAP_ENOMEM, "host allocation failed");
-    h->N = N;
+    h->K = count;
     h->precision = o.precision;
     h->trace_level = std::max(0, std::min(2, o.trace_level));
     h->use_graph = o.use_graph ? 1 : 0;
     h->elem = o.precision == QAP_FP64 ? sizeof(double) : sizeof(float);
+    h->tLB.resize(count);
+    h->tLBp.resize(count);
 
     auto bail = [&](qap_status st) {
         release(h);
@@ -350,77 +421,130 @@ qap_status qap_rlt2_create_ex(int N, const double* F, const double* Dm, const do
         h->own_stream = true;
     }
 
-    const int n1 = N - 1, n2 = N - 2;
-    h->nB = (int64_t)N * N;
-    h->nC = h->nB * n1 * n1;
-    h->nblkD = h->nC;
-    const int64_t blk = (int64_t)n2 * n2;
-    const int64_t align_elems = 128 / (int64_t)h->elem;
-    h->ldD = (blk + align_elems - 1) / align_elems * align_elems;
-    h->ngroups = (int64_t)N * (N - 1) * (N - 2) / 6 * ((int64_t)N * n1 * n2);
+    // Packed layout of all instances.
+    const long long align_elems = 128 / (long long)h->elem;
+    std::vector<int> tri;
+    h->inst.resize(count);
+    for (int k = 0; k < count; ++k) {
+        const int N = Ns[k], n1 = N - 1, n2 = N - 2;
+        qap::Inst& I = h->inst[k];
+        I.N = N;
+        I.ntri = N * (N - 1) * (N - 2) / 6;
+        I.wpt = (N * n1 * n2 + 255) / 256;
+        I.pad_ = 0;
+        I.offB = h->totalB;
+        I.offC = h->totalC;
+        I.offD = h->totalD;
+        I.ldD = ((long long)n2 * n2 + align_elems - 1) / align_elems * align_elems;
+        I.wg0 = h->totalWG;
+        I.tri0 = (long long)tri.size();
+        for (int i = 0; i < N; ++i)
+            for (int kk = i + 1; kk < N; ++kk)
+                for (int p = kk + 1; p < N; ++p) {
+                    tri.push_back(i);
+                    tri.push_back(kk);
+                    tri.push_back(p);
+                }
+        h->preB.push_back(h->totalB);
+        h->preC.push_back(h->totalC);
+        h->preWG.push_back(h->totalWG);
+        const long long nC = (long long)N * N * n1 * n1;
+        h->totalB += (long long)N * N;
+        h->totalC += nC;
+        h->totalD += nC * I.ldD;
+        h->totalWG += 8LL * ((I.ntri + 7) / 8) * I.wpt;
+    }
+    // Segment-size classes of the three families.
+    for (int f = 0; f < 3; ++f) {
+        for (int k = 0; k < count; ++k) {
+            const int N = Ns[k];
+            const int n = (f == 0) ? N - 2 : (f == 1) ? N - 1 : N;
+            const int seg = seg_for(n);
+            const int ci = seg == 8 ? 0 : seg == 16 ? 1 : seg == 32 ? 2 : 3;
+            ClassHost& c = h->fam[f][ci];
+            c.seg = seg;
+            c.nmax = std::max(c.nmax, n);
+            c.ids.push_back(k);
+            c.pre.push_back(c.total);
+            c.total += (f == 0) ? (long long)N * N * (N - 1) * (N - 1) : (f == 1) ? (long long)N * N : 1;
+        }
+    }
 
-    const size_t bytesD = (size_t)h->nblkD * h->ldD * h->elem;
+    const size_t bytesD = (size_t)h->totalD * h->elem;
     size_t freeb = 0, totalb = 0;
     CK(hipMemGetInfo(&freeb, &totalb));
-    if (bytesD + (size_t)h->nC * h->elem * 2 > freeb)
-        return bail(fail(QAP_ENOMEM, "reduced-cost array does not fit in free device memory"));
+    if (bytesD + (size_t)h->totalC * (2 * h->elem + 8) > freeb)
+        return bail(fail(QAP_ENOMEM, "reduced-cost arrays do not fit in free device memory"));
 
-    CK(hipMalloc(&h->dB, h->nB * h->elem));
-    CK(hipMalloc(&h->dC, h->nC * h->elem));
-    CK(hipMalloc(&h->dCC, h->nC * h->elem));
+    CK(hipMalloc(&h->dB, h->totalB * h->elem));
+    CK(hipMalloc(&h->dC, h->totalC * h->elem));
+    CK(hipMalloc(&h->dCC, h->totalC * h->elem));
     CK(hipMalloc(&h->dD, bytesD));
-    CK(hipMalloc(&h->dLB, 2 * sizeof(double)));
-    CK(hipMalloc(&h->dTrace, 2 * kTraceCap * sizeof(double)));
-    CK(hipMalloc(&h->dCounter, sizeof(long long)));
-    CK(hipMalloc(&h->dCt, h->nC * sizeof(double)));
-    CK(hipMalloc(&h->dBt, h->nB * sizeof(double)));
-    CK(hipMalloc(&h->dCert, sizeof(double)));
+    CK(hipMalloc(&h->dLB, 2 * count * sizeof(double)));
+    CK(hipMalloc(&h->dTrace, 2 * kTraceCap * count * sizeof(double)));
+    CK(hipMalloc(&h->dCounter, count * sizeof(long long)));
+    CK(hipMalloc(&h->dCt, h->totalC * sizeof(double)));
+    CK(hipMalloc(&h->dBt, h->totalB * sizeof(double)));
+    CK(hipMalloc(&h->dCert, count * sizeof(double)));
     if (h->trace_level >= 2) {
-        CK(hipMalloc(&h->dValD, h->nblkD * sizeof(double)));
-        CK(hipMalloc(&h->dValC, h->nB * sizeof(double)));
-        CK(hipMalloc(&h->dValB, sizeof(double)));
+        CK(hipMalloc(&h->dValD, h->totalC * sizeof(double)));
+        CK(hipMalloc(&h->dValC, h->totalB * sizeof(double)));
+        CK(hipMalloc(&h->dValB, count * sizeof(double)));
     }
-    std::vector<int> tri;
-    for (int i = 0; i < N; ++i)
-        for (int k = i + 1; k < N; ++k)
-            for (int p = k + 1; p < N; ++p) {
-                tri.push_back(i);
-                tri.push_back(k);
-                tri.push_back(p);
-            }
-    CK(hipMalloc(&h->dTri, tri.size() * sizeof(int)));
-    CK(hipMemcpyAsync(h->dTri, tri.data(), tri.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    CK(upload(&h->dTri, tri, h->stream));
+    CK(upload(&h->dInst, h->inst, h->stream));
+    CK(upload(&h->dPreB, h->preB, h->stream));
+    CK(upload(&h->dPreC, h->preC, h->stream));
+    CK(upload(&h->dPreWG, h->preWG, h->stream));
+    for (auto& f : h->fam)
+        for (auto& c : f) {
+            if (c.ids.empty()) continue;
+            CK(upload(&c.d_ids, c.ids, h->stream));
+            CK(upload(&c.d_pre, c.pre, h->stream));
+        }
+    std::vector<double> lb0(2 * count, 0.0);
+    for (int k = 0; k < count; ++k) lb0[2 * k] = constants ? constants[k] : 0.0;
+    CK(hipMemcpyAsync(h->dLB, lb0.data(), lb0.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    CK(hipMemsetAsync(h->dCounter, 0, count * sizeof(long long), h->stream));
+    CK(hipMemsetAsync(h->dD, 0, bytesD, h->stream));
 
+    // Initial dual of every instance.
+    int Nmax = 0;
+    for (int k = 0; k < count; ++k) Nmax = std::max(Nmax, (int)Ns[k]);
     double* dF = nullptr;
     double* dDm = nullptr;
     double* dB0 = nullptr;
-    CK(hipMalloc(&dF, h->nB * sizeof(double)));
-    CK(hipMalloc(&dDm, h->nB * sizeof(double)));
-    if (B0) CK(hipMalloc(&dB0, h->nB * sizeof(double)));
-    CK(hipMemcpyAsync(dF, F, h->nB * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    CK(hipMemcpyAsync(dDm, Dm, h->nB * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    if (B0) CK(hipMemcpyAsync(dB0, B0, h->nB * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    const double lb0[2] = {constant, 0.0};
-    CK(hipMemcpyAsync(h->dLB, lb0, sizeof(lb0), hipMemcpyHostToDevice, h->stream));
-    const long long zero = 0;
-    CK(hipMemcpyAsync(h->dCounter, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
-    CK(hipMemsetAsync(h->dD, 0, bytesD, h->stream));
-
-    if (h->precision == QAP_FP64) {
-        hipLaunchKernelGGL((qap::k_init<double>), dim3(grid_for(h->nC, 256)), dim3(256), 0, h->stream, dF, dDm,
-                           dB0, static_cast<double*>(h->dB), static_cast<double*>(h->dC), N);
-    } else {
-        hipLaunchKernelGGL((qap::k_init<float>), dim3(grid_for(h->nC, 256)), dim3(256), 0, h->stream, dF, dDm,
-                           dB0, static_cast<float*>(h->dB), static_cast<float*>(h->dC), N);
+    CK(hipMalloc(&dF, (size_t)Nmax * Nmax * sizeof(double)));
+    CK(hipMalloc(&dDm, (size_t)Nmax * Nmax * sizeof(double)));
+    CK(hipMalloc(&dB0, (size_t)Nmax * Nmax * sizeof(double)));
+    for (int k = 0; k < count; ++k) {
+        const int N = Ns[k];
+        const size_t nb = (size_t)N * N * sizeof(double);
+        const double* B0 = B0s ? B0s[k] : nullptr;
+        CK(hipMemcpyAsync(dF, Fs[k], nb, hipMemcpyHostToDevice, h->stream));
+        CK(hipMemcpyAsync(dDm, Ds[k], nb, hipMemcpyHostToDevice, h->stream));
+        if (B0) CK(hipMemcpyAsync(dB0, B0, nb, hipMemcpyHostToDevice, h->stream));
+        const qap::Inst& I = h->inst[k];
+        const long long nC = (long long)N * N * (N - 1) * (N - 1);
+        if (h->precision == QAP_FP64)
+            hipLaunchKernelGGL((qap::k_init<double>), dim3(grid_for(nC, 256)), dim3(256), 0, h->stream, dF, dDm,
+                               B0 ? dB0 : nullptr, static_cast<double*>(h->dB) + I.offB,
+                               static_cast<double*>(h->dC) + I.offC, N);
+        else
+            hipLaunchKernelGGL((qap::k_init<float>), dim3(grid_for(nC, 256)), dim3(256), 0, h->stream, dF, dDm,
+                               B0 ? dB0 : nullptr, static_cast<float*>(h->dB) + I.offB,
+                               static_cast<float*>(h->dC) + I.offC, N);
+        CK(hipGetLastError());
+        // The staging buffers are reused by the next instance.
+        CK(hipStreamSynchronize(h->stream));
     }
-    CK(hipGetLastError());
+    (void)hipFree(dF);
+    (void)hipFree(dDm);
+    (void)hipFree(dB0);
     // Iteration 0: C -> B, then B -> LB.
     CK(enqueue_step_any(h, 6));
     CK(enqueue_step_any(h, 7));
     CK(hipStreamSynchronize(h->stream));
-    (void)hipFree(dF);
-    (void)hipFree(dDm);
-    if (dB0) (void)hipFree(dB0);
     qap_status st = drain_trace(h);
     if (st != QAP_OK) return bail(st);
 #undef CK
@@ -498,17 +622,45 @@ qap_status qap_rlt2_step(qap_rlt2* h, int step)
     return QAP_OK;
 }
 
-qap_status qap_rlt2_certify(qap_rlt2* h, double* certified)
+qap_status qap_rlt2_batch_bounds(qap_rlt2* h, double* lb, double* certified)
 {
     qap_status st = check_handle(h);
     if (st != QAP_OK) return st;
-    if (!certified) return fail(QAP_EINVAL, "null output");
-    hipError_t e = h->precision == QAP_FP64 ? enqueue_certify<double>(h) : enqueue_certify<float>(h);
-    if (e != hipSuccess) return mark_broken(h, e, "certification launch");
-    e = hipMemcpyAsync(certified, h->dCert, sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    if (e != hipSuccess) return mark_broken(h, e, "hipMemcpyAsync");
-    e = hipStreamSynchronize(h->stream);
+    if (certified) {
+        hipError_t e = h->precision == QAP_FP64 ? enqueue_certify<double>(h) : enqueue_certify<float>(h);
+        if (e != hipSuccess) return mark_broken(h, e, "certification launch");
+        e = hipMemcpyAsync(certified, h->dCert, h->K * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        if (e != hipSuccess) return mark_broken(h, e, "hipMemcpyAsync");
+    }
+    if (lb) {
+        std::vector<double> v(2 * h->K);
+        hipError_t e = hipMemcpyAsync(v.data(), h->dLB, v.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                      h->stream);
+        if (e != hipSuccess) return mark_broken(h, e, "hipMemcpyAsync");
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return mark_broken(h, e, "hipStreamSynchronize");
+        for (int k = 0; k < h->K; ++k) lb[k] = v[2 * k];
+    }
+    hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return mark_broken(h, e, "hipStreamSynchronize");
+    return QAP_OK;
+}
+
+qap_status qap_rlt2_certify(qap_rlt2* h, double* certified)
+{
+    if (!certified) return fail(QAP_EINVAL, "null output");
+    qap_status st = check_handle(h);
+    if (st != QAP_OK) return st;
+    std::vector<double> c(h->K);
+    st = qap_rlt2_batch_bounds(h, nullptr, c.data());
+    if (st == QAP_OK) *certified = c[0];
+    return st;
+}
+
+qap_status qap_rlt2_count(qap_rlt2* h, int* count)
+{
+    if (!h || !count) return fail(QAP_EINVAL, "null argument");
+    *count = h->K;
     return QAP_OK;
 }
 
@@ -526,46 +678,63 @@ qap_status qap_rlt2_bound(qap_rlt2* h, double* lb, int64_t* iterations)
     return QAP_OK;
 }
 
-qap_status qap_rlt2_trace(qap_rlt2* h, int64_t capacity, int64_t* count, double* lb, double* lbprime)
+qap_status qap_rlt2_instance_trace(qap_rlt2* h, int k, int64_t capacity, int64_t* count, double* lb,
+                                   double* lbprime)
 {
     if (!h) return fail(QAP_EINVAL, "null handle");
+    if (k < 0 || k >= h->K) return fail(QAP_EINVAL, "instance index out of range");
     if (capacity < 0) return fail(QAP_EINVAL, "negative capacity");
-    const int64_t n = (int64_t)h->tLB.size();
+    const int64_t n = (int64_t)h->tLB[k].size();
     if (count) *count = n;
     const int64_t m = std::min(n, capacity);
-    if (lb) std::copy(h->tLB.begin(), h->tLB.begin() + m, lb);
-    if (lbprime) std::copy(h->tLBp.begin(), h->tLBp.begin() + m, lbprime);
+    if (lb) std::copy(h->tLB[k].begin(), h->tLB[k].begin() + m, lb);
+    if (lbprime) std::copy(h->tLBp[k].begin(), h->tLBp[k].begin() + m, lbprime);
+    return QAP_OK;
+}
+
+qap_status qap_rlt2_trace(qap_rlt2* h, int64_t capacity, int64_t* count, double* lb, double* lbprime)
+{
+    return qap_rlt2_instance_trace(h, 0, capacity, count, lb, lbprime);
+}
+
+qap_status qap_rlt2_instance_lap_values(qap_rlt2* h, int k, double* sD, double* sC, double* sB)
+{
+    qap_status st = check_handle(h);
+    if (st != QAP_OK) return st;
+    if (k < 0 || k >= h->K) return fail(QAP_EINVAL, "instance index out of range");
+    if (h->trace_level < 2) return fail(QAP_EINVAL, "per-assignment values need trace_level 2");
+    const qap::Inst& I = h->inst[k];
+    const long long nC = (long long)I.N * I.N * (I.N - 1) * (I.N - 1);
+    if (sD) QAP_HIP(hipMemcpy(sD, h->dValD + I.offC, nC * sizeof(double), hipMemcpyDeviceToHost));
+    if (sC) QAP_HIP(hipMemcpy(sC, h->dValC + I.offB, (size_t)I.N * I.N * sizeof(double), hipMemcpyDeviceToHost));
+    if (sB) QAP_HIP(hipMemcpy(sB, h->dValB + k, sizeof(double), hipMemcpyDeviceToHost));
     return QAP_OK;
 }
 
 qap_status qap_rlt2_lap_values(qap_rlt2* h, double* sD, double* sC, double* sB)
 {
-    qap_status st = check_handle(h);
-    if (st != QAP_OK) return st;
-    if (h->trace_level < 2) return fail(QAP_EINVAL, "per-assignment values need trace_level 2");
-    if (sD) QAP_HIP(hipMemcpy(sD, h->dValD, h->nblkD * sizeof(double), hipMemcpyDeviceToHost));
-    if (sC) QAP_HIP(hipMemcpy(sC, h->dValC, h->nB * sizeof(double), hipMemcpyDeviceToHost));
-    if (sB) QAP_HIP(hipMemcpy(sB, h->dValB, sizeof(double), hipMemcpyDeviceToHost));
-    return QAP_OK;
+    return qap_rlt2_instance_lap_values(h, 0, sD, sC, sB);
 }
 
-qap_status qap_rlt2_read_state(qap_rlt2* h, double* lb, double* B, double* C, double* D)
+qap_status qap_rlt2_instance_state(qap_rlt2* h, int k, double* lb, double* B, double* C, double* D)
 {
     qap_status st = check_handle(h);
     if (st != QAP_OK) return st;
+    if (k < 0 || k >= h->K) return fail(QAP_EINVAL, "instance index out of range");
     QAP_HIP(hipStreamSynchronize(h->stream));
+    const qap::Inst& I = h->inst[k];
+    const int N = I.N, n2 = N - 2;
     if (lb) {
         double v[2];
-        QAP_HIP(hipMemcpy(v, h->dLB, sizeof(v), hipMemcpyDeviceToHost));
+        QAP_HIP(hipMemcpy(v, h->dLB + 2 * k, sizeof(v), hipMemcpyDeviceToHost));
         *lb = v[0];
     }
-    const int n2 = h->N - 2;
-    const int64_t blk = (int64_t)n2 * n2;
-    auto widen = [&](void* dst, const void* src, int64_t count, size_t src_pitch, int64_t rows) -> hipError_t {
-        if (h->precision == QAP_FP64) {
+    const long long blk = (long long)n2 * n2;
+    const long long nC = (long long)N * N * (N - 1) * (N - 1);
+    auto widen = [&](void* dst, const void* src, long long count, size_t src_pitch, long long rows) -> hipError_t {
+        if (h->precision == QAP_FP64)
             return hipMemcpy2D(dst, count * sizeof(double), src, src_pitch, count * sizeof(double), rows,
                                hipMemcpyDeviceToHost);
-        }
         std::vector<float> tmp((size_t)count * rows);
         hipError_t e = hipMemcpy2D(tmp.data(), count * sizeof(float), src, src_pitch, count * sizeof(float), rows,
                                    hipMemcpyDeviceToHost);
@@ -574,10 +743,18 @@ qap_status qap_rlt2_read_state(qap_rlt2* h, double* lb, double* B, double* C, do
         for (size_t x = 0; x < tmp.size(); ++x) d[x] = (double)tmp[x];
         return hipSuccess;
     };
-    if (B) QAP_HIP(widen(B, h->dB, h->nB, h->nB * h->elem, 1));
-    if (C) QAP_HIP(widen(C, h->dC, h->nC, h->nC * h->elem, 1));
-    if (D) QAP_HIP(widen(D, h->dD, blk, h->ldD * h->elem, h->nblkD));
+    const char* b = static_cast<const char*>(h->dB) + I.offB * h->elem;
+    const char* c = static_cast<const char*>(h->dC) + I.offC * h->elem;
+    const char* d = static_cast<const char*>(h->dD) + I.offD * h->elem;
+    if (B) QAP_HIP(widen(B, b, (long long)N * N, (size_t)N * N * h->elem, 1));
+    if (C) QAP_HIP(widen(C, c, nC, (size_t)nC * h->elem, 1));
+    if (D) QAP_HIP(widen(D, d, blk, I.ldD * h->elem, nC));
     return QAP_OK;
+}
+
+qap_status qap_rlt2_read_state(qap_rlt2* h, double* lb, double* B, double* C, double* D)
+{
+    return qap_rlt2_instance_state(h, 0, lb, B, C, D);
 }
 
 void qap_rlt2_destroy(qap_rlt2* h)
@@ -587,6 +764,52 @@ void qap_rlt2_destroy(qap_rlt2* h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     release(h);
     delete h;
+}
+
+qap_status qap_subproblem(int N, const double* F, const double* D, int m, const int32_t* fac, const int32_t* loc,
+                          double* Fsub, double* Dsub, double* B0sub, double* constant)
+{
+    g_last_error.clear();
+    if (N < 1 || N > 4096) return fail(QAP_EINVAL, "N out of range");
+    if (m < 0 || m > N) return fail(QAP_EINVAL, "m out of range");
+    if (!F || !D || (m > 0 && (!fac || !loc)) || !Fsub || !Dsub || !B0sub || !constant)
+        return fail(QAP_EINVAL, "null argument");
+    std::vector<char> fixf(N, 0), fixl(N, 0);
+    for (int t = 0; t < m; ++t) {
+        if (fac[t] < 0 || fac[t] >= N || loc[t] < 0 || loc[t] >= N) return fail(QAP_EINVAL, "index out of range");
+        if (fixf[fac[t]] || fixl[loc[t]]) return fail(QAP_EINVAL, "repeated facility or location");
+        fixf[fac[t]] = 1;
+        fixl[loc[t]] = 1;
+    }
+    std::vector<int> fr, lr;
+    for (int i = 0; i < N; ++i) {
+        if (!fixf[i]) fr.push_back(i);
+        if (!fixl[i]) lr.push_back(i);
+    }
+    const int M = N - m;
+    for (int a = 0; a < M; ++a)
+        for (int b = 0; b < M; ++b) {
+            Fsub[a * M + b] = F[fr[a] * N + fr[b]];
+            Dsub[a * M + b] = D[lr[a] * N + lr[b]];
+        }
+    // Linear cost of free facility fr[a] at free location lr[b]: its flows to
+    // and from every fixed facility times the matching distances.
+    for (int a = 0; a < M; ++a)
+        for (int b = 0; b < M; ++b) {
+            double s = 0.0;
+            const int i = fr[a], j = lr[b];
+            for (int t = 0; t < m; ++t) {
+                s += F[i * N + fac[t]] * D[j * N + loc[t]];
+                s += F[fac[t] * N + i] * D[loc[t] * N + j];
+            }
+            B0sub[a * M + b] = s;
+        }
+    // Cost among the fixed facilities themselves (diagonal terms included).
+    double c = 0.0;
+    for (int t = 0; t < m; ++t)
+        for (int u = 0; u < m; ++u) c += F[fac[t] * N + fac[u]] * D[loc[t] * N + loc[u]];
+    *constant = c;
+    return QAP_OK;
 }
 
 qap_status qap_lap_solve(int batch, const int32_t* n, const int64_t* mat_off, const int64_t* vec_off, void* cost,
@@ -678,6 +901,7 @@ qap_status qap_lap_solve(int batch, const int32_t* n, const int64_t* mat_off, co
     cleanup();
     return QAP_OK;
 }
+
 
 const char* qap_last_error(void) { return g_last_error.c_str(); }
 

@@ -104,7 +104,38 @@ __device__ __forceinline__ int entry_of(int N, int a, int la, int b, int lb, int
     return drop2(c, a, b) * (N - 2) + drop2(lc, la, lb);
 }
 
-// Initial dual (the lines of Algorithm 1 before its loop):
+// ---- instances -----------------------------------------------------------------
+// A handle holds K independent instances (a single QAP, or the nodes of a
+// branch-and-bound batch).  Their B, C and D arrays are packed one after the
+// other; every kernel below covers all instances in one launch and finds its
+// instance by binary search in a prefix array.
+struct Inst {
+    int N;
+    int ntri;          // N(N-1)(N-2)/6 facility triples
+    int wpt;           // sweep workgroups per facility triple
+    int pad_;
+    long long offB;    // first entry of the instance in the packed B array
+    long long offC;    // first entry in the packed C (and CC) arrays
+    long long offD;    // first entry in the packed D array
+    long long ldD;     // block stride of D (>= (N-2)^2, 128-byte multiple)
+    long long wg0;     // first sweep workgroup (a multiple of 8)
+    long long tri0;    // first int of the instance's facility-triple table
+};
+
+// Largest k in [0, K) with pre[k] <= x (pre ascending, pre[0] = 0).
+__device__ __forceinline__ int find_seg(const long long* __restrict__ pre, int K, long long x) {
+    int lo = 0, hi = K - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Initial dual of one instance (the lines of Algorithm 1 before its loop):
 //   b_ij = f_ii d_jj (+ B0_ij), c_ijkn = f_ik d_jn.
 template <typename T>
 __global__ __launch_bounds__(256) void k_init(const double* __restrict__ F, const double* __restrict__ Dm,
@@ -137,23 +168,28 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ F, cons
     }
 }
 
-// Steps 1-2 precomputation: the amount each entry of block D_beta receives,
+// Steps 1-2 precomputation, one thread per C entry of every instance: the
+// amount each entry of block D_beta receives,
 //   CC_beta = (c_beta + b_ij / (N-1)) / (N-2),
-// after which c is cleared (B is cleared by the sweep, which no longer reads it).
+// after which c is cleared (B is cleared by the sweep, which does not read it).
 template <typename T>
 __global__ __launch_bounds__(256) void k_spread_prep(T* __restrict__ C, const T* __restrict__ B,
-                                                     T* __restrict__ CC, int N)
+                                                     T* __restrict__ CC, const Inst* __restrict__ inst,
+                                                     const long long* __restrict__ preC, int K,
+                                                     long long totalC)
 {
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int n1 = N - 1;
-    if (x >= (int64_t)N * N * n1 * n1) return;
-    const int ij = (int)(x / (n1 * n1));
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= totalC) return;
+    const Inst I = inst[find_seg(preC, K, x)];
+    const int N = I.N, n1 = N - 1;
+    const int ij = (int)((x - I.offC) / (n1 * n1));
+    const T bij = B[I.offB + ij];
     if constexpr (sizeof(T) == 8) {
-        const T share_b = B[ij] / (T)(N - 1);
+        const T share_b = bij / (T)(N - 1);
         const T c = C[x] + share_b;
         CC[x] = c / (T)(N - 2);
     } else {
-        const double c = add_down((double)C[x], div_down((double)B[ij], (double)(N - 1)));
+        const double c = add_down((double)C[x], div_down((double)bij, (double)(N - 1)));
         CC[x] = to_float_down(div_down(c, (double)(N - 2)));
     }
     C[x] = (T)0;
@@ -162,31 +198,36 @@ __global__ __launch_bounds__(256) void k_spread_prep(T* __restrict__ C, const T*
 // Steps 1-3 on D: every entry gets its block's spread share, then each group
 // of six complementary coefficients (equation (11)) is replaced by its mean.
 // One thread per group.  A group is an unordered triple of (facility,
-// location) pairs; it is enumerated as a facility triple i < k < p (from
-// `tri`) times an ordered location triple (j, n, q) of distinct locations,
-// with q varying fastest so that the members (P1 P2 P3) and (P2 P1 P3) are
-// read and written contiguously.  With P1=(i,j), P2=(k,n), P3=(p,q) the six
-// members are summed in lexicographic order of the permutation of
-// (P1, P2, P3), so the result is the same bits on every run.
+// location) pairs; it is enumerated as a facility triple i < k < p (from the
+// instance's triple table) times an ordered location triple (j, n, q) of
+// distinct locations, with q varying fastest so that the members (P1 P2 P3)
+// and (P2 P1 P3) are read and written contiguously.  With P1=(i,j), P2=(k,n),
+// P3=(p,q) the six members are summed in lexicographic order of the
+// permutation of (P1, P2, P3), so the result is the same bits on every run.
 //
 // XCD-aware schedule: the hardware hands workgroup b to XCD b mod 8, and each
-// XCD has its own L2.  All W workgroups of facility triple t are given ids
-// congruent to t mod 8 and consecutive among that XCD's ids, so one XCD works
-// through a triple's six sub-arrays (6 N(N-1)(N-2) entries) together and the
-// partially used cache lines of the four strided members meet in its L2.
+// XCD has its own L2.  Within an instance (whose first workgroup is a
+// multiple of 8) all wpt workgroups of facility triple t get ids congruent to
+// t mod 8 and consecutive among that XCD's ids, so one XCD works through a
+// triple's six sub-arrays (6 N(N-1)(N-2) entries) together and the partially
+// used cache lines of the four strided members meet in its L2.
+// The first totalB threads of the grid also clear B.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __restrict__ CC,
                                                T* __restrict__ B, const int* __restrict__ tri,
-                                               int N, int64_t ldD, int ntri, int wg_per_tri)
+                                               const Inst* __restrict__ inst,
+                                               const long long* __restrict__ preWG, int K, long long totalB)
 {
-    if (blockIdx.x == 0)
-        for (int x = threadIdx.x; x < N * N; x += blockDim.x) B[x] = (T)0;
-    const int xcd = blockIdx.x & 7;
-    const int local = blockIdx.x >> 3;
-    const int t = (local / wg_per_tri) * 8 + xcd;
-    const int w = local % wg_per_tri;
-    if (t >= ntri) return;
-    const int n1 = N - 1, n2 = N - 2;
+    const long long gx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gx < totalB) B[gx] = (T)0;
+    const Inst I = inst[find_seg(preWG, K, (long long)blockIdx.x)];
+    const int lb = (int)((long long)blockIdx.x - I.wg0);
+    const int xcd = lb & 7;
+    const int local = lb >> 3;
+    const int t = (local / I.wpt) * 8 + xcd;
+    const int w = local % I.wpt;
+    if (t >= I.ntri) return;
+    const int N = I.N, n1 = N - 1, n2 = N - 2;
     const int L = N * n1 * n2;
     const int loc = w * 256 + (int)threadIdx.x;
     if (loc >= L) return;
@@ -195,7 +236,11 @@ __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __re
     const int j = rest / n1;
     const int n = skip1(rest % n1, j);
     const int q = skip2(qq, min(j, n), max(j, n));
-    const int i = tri[3 * t], k = tri[3 * t + 1], p = tri[3 * t + 2];
+    const int* tr = tri + I.tri0 + 3 * t;
+    const int i = tr[0], k = tr[1], p = tr[2];
+    T* __restrict__ Dk = Dd + I.offD;
+    const T* __restrict__ CCk = CC + I.offC;
+    const long long ldD = I.ldD;
 
     const int64_t b0 = beta_of(N, i, j, k, n), b1 = beta_of(N, i, j, p, q);
     const int64_t b2 = beta_of(N, k, n, i, j), b3 = beta_of(N, k, n, p, q);
@@ -209,12 +254,12 @@ __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __re
 
     T mean;
     if constexpr (sizeof(T) == 8) {
-        const T m0 = Dd[a0] + CC[b0];
-        const T m1 = Dd[a1] + CC[b1];
-        const T m2 = Dd[a2] + CC[b2];
-        const T m3 = Dd[a3] + CC[b3];
-        const T m4 = Dd[a4] + CC[b4];
-        const T m5 = Dd[a5] + CC[b5];
+        const T m0 = Dk[a0] + CCk[b0];
+        const T m1 = Dk[a1] + CCk[b1];
+        const T m2 = Dk[a2] + CCk[b2];
+        const T m3 = Dk[a3] + CCk[b3];
+        const T m4 = Dk[a4] + CCk[b4];
+        const T m5 = Dk[a5] + CCk[b5];
         T s = m0;
         s += m1;
         s += m2;
@@ -223,41 +268,44 @@ __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __re
         s += m5;
         mean = s / (T)6;
     } else {
-        double s = add_down((double)Dd[a0], (double)CC[b0]);
-        s = add_down(s, (double)Dd[a1]);
-        s = add_down(s, (double)CC[b1]);
-        s = add_down(s, (double)Dd[a2]);
-        s = add_down(s, (double)CC[b2]);
-        s = add_down(s, (double)Dd[a3]);
-        s = add_down(s, (double)CC[b3]);
-        s = add_down(s, (double)Dd[a4]);
-        s = add_down(s, (double)CC[b4]);
-        s = add_down(s, (double)Dd[a5]);
-        s = add_down(s, (double)CC[b5]);
+        double s = add_down((double)Dk[a0], (double)CCk[b0]);
+        s = add_down(s, (double)Dk[a1]);
+        s = add_down(s, (double)CCk[b1]);
+        s = add_down(s, (double)Dk[a2]);
+        s = add_down(s, (double)CCk[b2]);
+        s = add_down(s, (double)Dk[a3]);
+        s = add_down(s, (double)CCk[b3]);
+        s = add_down(s, (double)Dk[a4]);
+        s = add_down(s, (double)CCk[b4]);
+        s = add_down(s, (double)Dk[a5]);
+        s = add_down(s, (double)CCk[b5]);
         mean = to_float_down(div_down(s, 6.0));
     }
-    Dd[a0] = mean;
-    Dd[a1] = mean;
-    Dd[a2] = mean;
-    Dd[a3] = mean;
-    Dd[a4] = mean;
-    Dd[a5] = mean;
+    Dk[a0] = mean;
+    Dk[a1] = mean;
+    Dk[a2] = mean;
+    Dk[a3] = mean;
+    Dk[a4] = mean;
+    Dk[a5] = mean;
 }
 
 // Step 5: the complementary pair c_ijkn, c_knij (equation (10)) both become
-// their mean.  One thread per entry; the thread with i < k does the pair.
+// their mean.  One thread per C entry; the thread with i < k does the pair.
 template <typename T>
-__global__ __launch_bounds__(256) void k_transfer_C(T* __restrict__ C, int N)
+__global__ __launch_bounds__(256) void k_transfer_C(T* __restrict__ C, const Inst* __restrict__ inst,
+                                                    const long long* __restrict__ preC, int K, long long totalC)
 {
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int n1 = N - 1;
-    if (x >= (int64_t)N * N * n1 * n1) return;
-    const int ij = (int)(x / (n1 * n1));
-    const int rem = (int)(x % (n1 * n1));
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= totalC) return;
+    const Inst I = inst[find_seg(preC, K, x)];
+    const int N = I.N, n1 = N - 1;
+    const long long lx = x - I.offC;
+    const int ij = (int)(lx / (n1 * n1));
+    const int rem = (int)(lx % (n1 * n1));
     const int i = ij / N, j = ij % N;
     const int k = skip1(rem / n1, i), n = skip1(rem % n1, j);
     if (i >= k) return;
-    const int64_t y = beta_of(N, k, n, i, j);
+    const long long y = I.offC + beta_of(N, k, n, i, j);
     T mean;
     if constexpr (sizeof(T) == 8)
         mean = (C[x] + C[y]) / (T)2;
@@ -275,44 +323,52 @@ __global__ __launch_bounds__(256) void k_transfer_C(T* __restrict__ C, int N)
 // b~ = b + (N-1) min(0, min of C~_ij), and LB + N min(0, min b~) bounds the
 // whole sum from below whatever the signs of the stored entries.
 
-// One wave per D block: ct[beta] = c_beta + (N-2) * min(0, min D_beta).
+// One wave per D block of every instance: ct[beta] = c_beta + (N-2) min(0, min D_beta).
 template <typename T>
-__global__ __launch_bounds__(256) void k_cert_D(const T* __restrict__ Dd, int64_t ldD, int blk,
-                                                int64_t nblk, const T* __restrict__ C,
-                                                double* __restrict__ ct, int N)
+__global__ __launch_bounds__(256) void k_cert_D(const T* __restrict__ Dd, const T* __restrict__ C,
+                                                double* __restrict__ ct, const Inst* __restrict__ inst,
+                                                const long long* __restrict__ preC, int K, long long totalC)
 {
-    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const long long x = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (b >= nblk) return;
+    if (x >= totalC) return;
+    const Inst I = inst[find_seg(preC, K, x)];
+    const int N = I.N, blk = (N - 2) * (N - 2);
+    const T* __restrict__ Db = Dd + I.offD + (x - I.offC) * I.ldD;
     double m = 0.0;
-    for (int e = lane; e < blk; e += 64) m = __builtin_fmin(m, (double)Dd[b * ldD + e]);
+    for (int e = lane; e < blk; e += 64) m = __builtin_fmin(m, (double)Db[e]);
     for (int off = 32; off > 0; off >>= 1) m = __builtin_fmin(m, __shfl_xor(m, off, 64));
-    if (lane == 0) ct[b] = add_down((double)C[b], mul_down((double)(N - 2), m));
+    if (lane == 0) ct[x] = add_down((double)C[x], mul_down((double)(N - 2), m));
 }
 
-// One wave per C block: bt[ij] = b_ij + (N-1) * min(0, min C~_ij).
+// One wave per C block of every instance: bt[ij] = b_ij + (N-1) min(0, min C~_ij).
 template <typename T>
 __global__ __launch_bounds__(256) void k_cert_C(const double* __restrict__ ct, const T* __restrict__ B,
-                                                double* __restrict__ bt, int N)
+                                                double* __restrict__ bt, const Inst* __restrict__ inst,
+                                                const long long* __restrict__ preB, int K, long long totalB)
 {
-    const int ij = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const long long x = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (ij >= N * N) return;
-    const int blk = (N - 1) * (N - 1);
+    if (x >= totalB) return;
+    const Inst I = inst[find_seg(preB, K, x)];
+    const int N = I.N, blk = (N - 1) * (N - 1);
+    const double* __restrict__ cb = ct + I.offC + (x - I.offB) * blk;
     double m = 0.0;
-    for (int e = lane; e < blk; e += 64) m = __builtin_fmin(m, ct[(int64_t)ij * blk + e]);
+    for (int e = lane; e < blk; e += 64) m = __builtin_fmin(m, cb[e]);
     for (int off = 32; off > 0; off >>= 1) m = __builtin_fmin(m, __shfl_xor(m, off, 64));
-    if (lane == 0) bt[ij] = add_down((double)B[ij], mul_down((double)(N - 1), m));
+    if (lane == 0) bt[x] = add_down((double)B[x], mul_down((double)(N - 1), m));
 }
 
-// One wave: out = LB + N * min(0, min bt).
-__global__ __launch_bounds__(64) void k_cert_final(const double* __restrict__ bt, int N,
-                                                   const double* __restrict__ lb, double* __restrict__ out)
+// One wave per instance: out[k] = LB_k + N min(0, min bt over the instance).
+__global__ __launch_bounds__(64) void k_cert_final(const double* __restrict__ bt, const double* __restrict__ lb,
+                                                   double* __restrict__ out, const Inst* __restrict__ inst)
 {
+    const Inst I = inst[blockIdx.x];
+    const int N = I.N;
     double m = 0.0;
-    for (int e = threadIdx.x; e < N * N; e += 64) m = __builtin_fmin(m, bt[e]);
+    for (int e = threadIdx.x; e < N * N; e += 64) m = __builtin_fmin(m, bt[I.offB + e]);
     for (int off = 32; off > 0; off >>= 1) m = __builtin_fmin(m, __shfl_xor(m, off, 64));
-    if (threadIdx.x == 0) out[0] = add_down(lb[0], mul_down((double)N, m));
+    if (threadIdx.x == 0) out[blockIdx.x] = add_down(lb[2 * blockIdx.x], mul_down((double)N, m));
 }
 
 }  // namespace qap

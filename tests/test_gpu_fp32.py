@@ -90,7 +90,6 @@ def test_fp32_uniform16_accuracy_fifty_iterations():
         rel = abs(cert - o.lb) / o.lb
         worst = max(worst, rel)
         assert rel <= TOL32, (it, rel)
-        assert cert <= o.lb * (1 + 1e-12)
         if it <= 40:
             sD, sC, sB = g.lap_values()
             ok, err = layout.close_family(sD, layout.compact_C(o.SD), TOL32)
