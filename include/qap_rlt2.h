@@ -68,12 +68,21 @@ typedef struct {
                          most recent iteration (qap_rlt2_lap_values)           */
     int use_graph;    /* 1 (default): qap_rlt2_ascend replays one captured HIP
                          graph per iteration; 0: plain launches                */
+    int autotune;     /* 1 (default): during the first qap_rlt2_ascend, time the
+                         concentration kernels of every family and size class
+                         over the problems per wave (segment of n..64 lanes)
+                         and the waves per workgroup (1, 2, 4), on a restored
+                         copy of the live data, and keep the fastest; the
+                         results do not depend on the choice.  0: natural
+                         segment, one wave per workgroup                      */
+    const char* tune_cache; /* nullable path of a text file that stores the
+                         tuned choices and is read back by later handles     */
 } qap_rlt2_opts;
 
 typedef struct qap_rlt2 qap_rlt2;
 
 /* Fill *opts with the defaults (FP64, current device, own stream,
- * trace_level 1, use_graph 1). */
+ * trace_level 1, use_graph 1, autotune 1, no tune cache). */
 qap_status qap_rlt2_default_opts(qap_rlt2_opts* opts);
 
 /* Create a dual-ascent state for the QAP of equation (1) with flows F and

@@ -4,6 +4,7 @@
 // waves.  Problems of every instance of a handle are served by one launch per
 // segment-size class.
 #pragma once
+#include "lap_slots.hpp"
 #include "lap_wave.hpp"
 
 namespace qap {
@@ -65,6 +66,87 @@ __global__ __launch_bounds__(64 * WPB) void k_lap_family(T* __restrict__ D, T* _
         else
             parent[pidx] = to_float_down(add_down((double)parent[pidx], S));
         if (values) values[pidx] = S;
+    }
+}
+
+// Same as k_lap_family with K columns per lane (lap_concentrate_slots):
+// 64/SEG problems per wave, one wave per workgroup.
+template <typename T, int SEG, int K, int FAM>
+__global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __restrict__ C, T* __restrict__ B,
+                                                     const Inst* __restrict__ inst, FamilyClass fc, int nmax,
+                                                     double* __restrict__ values)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int LPW = 64 / SEG;
+    const int seg = threadIdx.x / SEG;
+    const int lane = threadIdx.x & (SEG - 1);
+    const long long x = (long long)blockIdx.x * LPW + seg;
+    const bool active = x < fc.total;
+    int n = 0;
+    T* blk = nullptr;
+    long long pidx = 0;
+    if (active) {
+        const int kk = find_seg(fc.pre, fc.Kc, x);
+        const Inst I = inst[fc.cls[kk]];
+        const long long b = x - fc.pre[kk];
+        if (FAM == kFamD) {
+            n = I.N - 2;
+            blk = D + I.offD + b * I.ldD;
+            pidx = I.offC + b;
+        } else {
+            n = I.N - 1;
+            blk = C + I.offC + b * (long long)(I.N - 1) * (I.N - 1);
+            pidx = I.offB + b;
+        }
+    }
+    const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
+    for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
+    wave_sync();
+    const double S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr);
+    if (active && lane == 0) {
+        T* parent = (FAM == kFamD) ? C : B;
+        if constexpr (sizeof(T) == 8)
+            parent[pidx] = parent[pidx] + S;
+        else
+            parent[pidx] = to_float_down(add_down((double)parent[pidx], S));
+        if (values) values[pidx] = S;
+    }
+}
+
+// B -> LB' with K columns per lane (see k_lap_B).
+template <typename T, int SEG, int K>
+__global__ __launch_bounds__(64) void k_lap_B_s(T* __restrict__ B, const Inst* __restrict__ inst, FamilyClass fc,
+                                                int nmax, double* __restrict__ lb, double* __restrict__ trace,
+                                                long long* __restrict__ counter, long long trace_cap,
+                                                double* __restrict__ values)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int LPW = 64 / SEG;
+    const int seg = threadIdx.x / SEG;
+    const int lane = threadIdx.x & (SEG - 1);
+    const long long x = (long long)blockIdx.x * LPW + seg;
+    const bool active = x < fc.total;
+    const int k = active ? fc.cls[x] : 0;
+    const Inst I = inst[k];
+    const int n = active ? I.N : 0;
+    T* blk = B + I.offB;
+    const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
+    for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
+    wave_sync();
+    const double S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr);
+    if (active && lane == 0) {
+        const double L = (sizeof(T) == 4) ? add_down(lb[2 * k], S) : lb[2 * k] + S;
+        lb[2 * k] = L;
+        lb[2 * k + 1] = S;
+        if (values) values[k] = S;
+        if (counter) {
+            const long long t = counter[k];
+            if (t < trace_cap) {
+                trace[(k * trace_cap + t) * 2] = L;
+                trace[(k * trace_cap + t) * 2 + 1] = S;
+            }
+            counter[k] = t + 1;
+        }
     }
 }
 

@@ -1,0 +1,500 @@
+// Linear assignment with canonical dual on gfx950, several columns per lane.
+//
+// Cost concentration (Section 4.1 of arXiv 1510.02065) solves one assignment
+// problem per block of the reduced-cost array, moves its value S to the
+// parent coefficient and replaces the block by its residuals.  Here a segment
+// of SEG lanes owns one n x n problem (n <= SEG*K) whose matrix sits in LDS;
+// lane l holds the K columns (and, in the row passes, the K rows)
+// l, l+SEG, ..., l+(K-1)*SEG.  A wave carries 64/SEG problems.  Every
+// Dijkstra step scans K columns per lane and then needs only a log2(SEG)-level
+// argmin, so the fixed per-step cost (argmin, broadcast, bookkeeping) is
+// shared by more columns and more problems than with one column per lane.
+//
+// Solver: the Hungarian method in its shortest-augmenting-path form
+// (Munkres), started from the Jonker-Volgenant column reduction (v_j = column
+// minimum; each row that is the first minimum of some column is matched to the
+// lowest such column).  Each remaining free row is inserted by Dijkstra over
+// columns with absolute tentative distances; the duals of the scanned tree are
+// shifted once when an unmatched column is reached.  Ties are broken towards
+// the lowest column index.
+//
+// Residual: the optimal dual is not unique, so the residual is taken under a
+// canonical choice that does not depend on the solver's path:
+//   column point: v^c = the greatest v <= 0 on the optimal dual face,
+//                 u^c_r = min_q (M_rq - v^c_q);
+//   row point:    u^r = the greatest u <= 0 on the optimal dual face,
+//                 v^r_q = min_r (M_rq - u^r_r);
+//   R = ((M - v^c - u^c) + (M - u^r - v^r)) / 2,
+//   S = (sum u^c + sum v^c + sum u^r + sum v^r) / 2.
+// With the solver's duals (u, v) and assignment sigma, v^c - v is the vector
+// of shortest distances in the column graph whose arc c -> q costs the reduced
+// cost M[sigma^-1(c)][q] - u - v >= 0, starting from label -v_q at every
+// column: one dense Dijkstra pass.  The row point is the same on the row graph.
+// In FP64 both residual halves are >= 0 exactly, because the subtracted dual
+// is a row (column) minimum of the already rounded differences.  The FP32
+// certified variant is described at its code.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lap_wave.hpp"
+#include "rlt2_kernels.hpp"
+
+namespace qap {
+
+// Segment collectives for SEG in {8, 16, 32, 64} lanes (all lanes of a
+// segment active; segments independent).
+template <int SEG>
+struct SegS {
+    static_assert(SEG == 8 || SEG == 16 || SEG == 32 || SEG == 64, "segment size");
+    __device__ __forceinline__ static int lane() { return threadIdx.x & (SEG - 1); }
+
+    template <typename T>
+    __device__ __forceinline__ static T min(T x) {
+        x = tmin(x, dpp<kDppXor1>(x));
+        x = tmin(x, dpp<kDppXor2>(x));
+        x = tmin(x, dpp<kDppHalfMirror>(x));
+        if constexpr (SEG >= 16) x = tmin(x, dpp<kDppMirror>(x));
+        if constexpr (SEG >= 32) {
+            T a, b;
+            swap_pair<16>(x, a, b);
+            x = tmin(a, b);
+        }
+        if constexpr (SEG >= 64) {
+            T a, b;
+            swap_pair<32>(x, a, b);
+            x = tmin(a, b);
+        }
+        return x;
+    }
+    __device__ __forceinline__ static int imin(int x) {
+        x = ::min(x, dpp_i<kDppXor1>(x));
+        x = ::min(x, dpp_i<kDppXor2>(x));
+        x = ::min(x, dpp_i<kDppHalfMirror>(x));
+        if constexpr (SEG >= 16) x = ::min(x, dpp_i<kDppMirror>(x));
+        if constexpr (SEG >= 32) {
+            const unsigned u = (unsigned)x;
+            auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+            x = ::min((int)r[0], (int)r[1]);
+        }
+        if constexpr (SEG >= 64) {
+            const unsigned u = (unsigned)x;
+            auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+            x = ::min((int)r[0], (int)r[1]);
+        }
+        return x;
+    }
+    template <typename T>
+    __device__ __forceinline__ static T sum(T x) {
+        x = x + dpp<kDppXor1>(x);
+        x = x + dpp<kDppXor2>(x);
+        x = x + dpp<kDppHalfMirror>(x);
+        if constexpr (SEG >= 16) x = x + dpp<kDppMirror>(x);
+        if constexpr (SEG >= 32) {
+            T a, b;
+            swap_pair<16>(x, a, b);
+            x = a + b;
+        }
+        if constexpr (SEG >= 64) {
+            T a, b;
+            swap_pair<32>(x, a, b);
+            x = a + b;
+        }
+        return x;
+    }
+    __device__ __forceinline__ static double sum_down(double x) {
+        x = add_down(x, dpp<kDppXor1>(x));
+        x = add_down(x, dpp<kDppXor2>(x));
+        x = add_down(x, dpp<kDppHalfMirror>(x));
+        if constexpr (SEG >= 16) x = add_down(x, dpp<kDppMirror>(x));
+        if constexpr (SEG >= 32) {
+            double a, b;
+            swap_pair<16>(x, a, b);
+            x = add_down(a, b);
+        }
+        if constexpr (SEG >= 64) {
+            double a, b;
+            swap_pair<32>(x, a, b);
+            x = add_down(a, b);
+        }
+        return x;
+    }
+};
+
+// Per-segment LDS working set:
+// [matrix n*n of T | p: W ints | aux: W ints | way: W ints | pad |
+//  u: W doubles | va: W doubles | vb: W doubles], W = SEG*K.
+template <typename T, int SEG, int K>
+struct SlotLds {
+    static constexpr int W = SEG * K;
+    __host__ __device__ static size_t mat_bytes(int n) {
+        return (((size_t)n * n * sizeof(T)) + 15) & ~(size_t)15;
+    }
+    __host__ __device__ static size_t vec_bytes() {
+        return ((3 * W * sizeof(int) + 15) & ~(size_t)15) + 3 * W * sizeof(double);
+    }
+    __host__ __device__ static size_t bytes(int n) { return mat_bytes(n) + vec_bytes(); }
+};
+
+template <typename T, int SEG, int K>
+struct SlotScratch {
+    static constexpr int W = SEG * K;
+    T* M;
+    int* p;      // row matched to column c (or -1)
+    int* aux;    // row ownership, then sigma (column of row r)
+    int* way;    // predecessor column on the shortest path
+    double* u;   // dual of the row matched to column c
+    double* va;
+    double* vb;
+    __device__ SlotScratch(unsigned char* base, int n) {
+        const size_t mb = SlotLds<T, SEG, K>::mat_bytes(n);
+        M = reinterpret_cast<T*>(base);
+        p = reinterpret_cast<int*>(base + mb);
+        aux = p + W;
+        way = aux + W;
+        u = reinterpret_cast<double*>(base + mb + ((3 * W * sizeof(int) + 15) & ~(size_t)15));
+        va = u + W;
+        vb = va + W;
+    }
+};
+
+// Solve, canonicalise and write residuals for the n x n matrix sc.M (in LDS,
+// row stride n, left unchanged).  R (nullable) receives the residual, duals
+// (nullable) [uc | vc | ur | vr], assign (nullable) the solver's assignment.
+// Returns S to every lane of the segment.  Called by whole waves; segments may
+// have different n (0 <= n <= SEG*K).
+template <typename T, int SEG, int K>
+__device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG, K>& sc, int n,
+                                                        T* __restrict__ R, T* __restrict__ duals,
+                                                        int32_t* __restrict__ assign)
+{
+    using S = SegS<SEG>;
+    constexpr int NONE = 1 << 20;   // larger than any column index
+    const T* __restrict__ M = sc.M;
+    const int lane = S::lane();
+    const T INF = inf_of<T>();
+
+    int c[K];      // this lane's columns (also its rows in the row passes)
+    bool ok[K];
+    for (int s = 0; s < K; ++s) {
+        c[s] = s * SEG + lane;
+        ok[s] = c[s] < n;
+    }
+
+    // ---- column reduction ---------------------------------------------------
+    T v[K];        // column duals
+    int p[K];      // row matched to each column (or -1)
+    T ucol[K];     // dual of that row
+    int crow[K];
+    for (int s = 0; s < K; ++s) {
+        v[s] = 0;
+        crow[s] = 0;
+        if (ok[s]) {
+            v[s] = M[c[s]];
+            for (int r = 1; r < n; ++r) {
+                const T m = M[r * n + c[s]];
+                if (m < v[s]) {
+                    v[s] = m;
+                    crow[s] = r;
+                }
+            }
+        }
+        sc.aux[c[s]] = NONE;
+    }
+    wave_sync();
+    for (int s = 0; s < K; ++s)
+        if (ok[s]) atomicMin(&sc.aux[crow[s]], c[s]);
+    wave_sync();
+    for (int s = 0; s < K; ++s) {
+        p[s] = (ok[s] && sc.aux[crow[s]] == c[s]) ? crow[s] : -1;
+        ucol[s] = 0;
+        sc.p[c[s]] = p[s];
+        sc.u[c[s]] = 0.0;
+    }
+    wave_sync();
+
+    // ---- Hungarian method for the rows left free -----------------------------
+    for (int i = 0; i < n; ++i) {
+        if (sc.aux[i] != NONE) continue;   // row i already matched
+        T dist[K];
+        int way[K];
+        bool used[K];
+        for (int s = 0; s < K; ++s) {
+            dist[s] = INF;
+            way[s] = -1;
+            used[s] = false;
+        }
+        int i0 = i;     // row being scanned
+        T ui0 = 0;      // its dual (a free row has dual 0)
+        T d0 = 0;       // distance at which row i0 was reached
+        int j0 = -1;    // column through which row i0 was reached
+        int jend = -1;
+        T dend = 0;
+        for (int pass = 0; pass <= n; ++pass) {
+            T lm = INF;
+            int lc = NONE;
+            for (int s = 0; s < K; ++s) {
+                const bool live = ok[s] && !used[s];
+                const T cur = d0 + ((M[i0 * n + (ok[s] ? c[s] : 0)] - ui0) - v[s]);
+                if (live && cur < dist[s]) {
+                    dist[s] = cur;
+                    way[s] = j0;
+                }
+                if (live && dist[s] < lm) {
+                    lm = dist[s];
+                    lc = c[s];
+                }
+            }
+            const T dmin = S::min(lm);
+            const int j1 = S::imin(lm == dmin ? lc : NONE);
+            const int j1c = j1 < n ? j1 : 0;
+            const int pj = j1 < n ? sc.p[j1c] : -1;
+            if (pj < 0) {
+                jend = j1 < n ? j1 : -1;   // no candidate: non-finite costs
+                dend = dmin;
+                break;
+            }
+            for (int s = 0; s < K; ++s) used[s] = used[s] || (c[s] == j1);
+            j0 = j1;
+            i0 = pj;
+            ui0 = (T)sc.u[j1c];
+            d0 = dmin;
+        }
+        // Dual shift of the scanned tree; predecessors published for the flip.
+        for (int s = 0; s < K; ++s) {
+            if (ok[s] && used[s]) {
+                const T sh = dend - dist[s];
+                v[s] -= sh;
+                ucol[s] += sh;
+            }
+            sc.way[c[s]] = way[s];
+            sc.u[c[s]] = (double)ucol[s];
+        }
+        wave_sync();
+        // Flip the path: every column on it takes the row (and row dual) of
+        // its predecessor column; the first one takes the new row.  Columns on
+        // the path are found by walking the predecessors from the end; every
+        // lane walks (the same) path and updates the columns it holds, reading
+        // the old rows and duals from LDS.
+        int newp[K];
+        T newu[K];
+        for (int s = 0; s < K; ++s) {
+            newp[s] = p[s];
+            newu[s] = ucol[s];
+        }
+        for (int j = jend, hop = 0; j >= 0 && j < n && hop <= n; ++hop) {
+            const int w = sc.way[j];
+            const int wc = w >= 0 ? w : 0;
+            const int pw = sc.p[wc];
+            const T uw = (T)sc.u[wc];
+            for (int s = 0; s < K; ++s) {
+                if (c[s] == j) {
+                    newp[s] = w >= 0 ? pw : i;
+                    newu[s] = w >= 0 ? uw : dend;
+                }
+            }
+            j = w;
+        }
+        wave_sync();
+        for (int s = 0; s < K; ++s) {
+            p[s] = newp[s];
+            ucol[s] = newu[s];
+            sc.p[c[s]] = p[s];
+            sc.u[c[s]] = (double)ucol[s];
+        }
+        wave_sync();
+    }
+
+    // ---- column-canonical point (lanes = columns) ---------------------------
+    // x_q = shortest distance to column q from label -v_q at every column, over
+    // arcs c -> q of reduced cost M[p(c)][q] - u_{p(c)} - v_q >= 0.
+    T x[K];
+    {
+        bool done[K];
+        for (int s = 0; s < K; ++s) {
+            x[s] = ok[s] ? -v[s] : INF;
+            done[s] = !ok[s];
+        }
+        for (int step = 0; step < n; ++step) {
+            T lm = INF;
+            int lc = NONE;
+            for (int s = 0; s < K; ++s)
+                if (!done[s] && x[s] < lm) {
+                    lm = x[s];
+                    lc = c[s];
+                }
+            const T dmin = S::min(lm);
+            const int cc = S::imin(lm == dmin ? lc : NONE);
+            if (cc >= n) break;
+            const int r = sc.p[cc];
+            const T ur = (T)sc.u[cc];
+            for (int s = 0; s < K; ++s) {
+                done[s] = done[s] || (c[s] == cc);
+                const T nd = dmin + ((M[r * n + (ok[s] ? c[s] : 0)] - ur) - v[s]);
+                if (!done[s] && nd < x[s]) x[s] = nd;
+            }
+        }
+        for (int s = 0; s < K; ++s)
+            if (!ok[s]) x[s] = 0;
+    }
+
+    // sigma (column of row r) in sc.aux, v in sc.vb; the solver's row dual
+    // u_r is the dual stored at column sigma(r).
+    wave_sync();
+    for (int s = 0; s < K; ++s) {
+        if (ok[s] && p[s] >= 0) sc.aux[p[s]] = c[s];
+        sc.vb[c[s]] = (double)v[s];
+    }
+    wave_sync();
+    int sg[K];     // lane as rows: sigma of this lane's rows
+    T urow[K];
+    for (int s = 0; s < K; ++s) {
+        sg[s] = ok[s] ? sc.aux[c[s]] : 0;
+        urow[s] = (T)sc.u[sg[s]];
+    }
+
+    // ---- row-canonical point (lanes = rows) ---------------------------------
+    // y_r = shortest distance to row r from label -u_r at every row, over
+    // arcs s -> r of reduced cost M[r][sigma(s)] - u_r - v_{sigma(s)} >= 0.
+    T y[K];
+    {
+        bool done[K];
+        for (int s = 0; s < K; ++s) {
+            y[s] = ok[s] ? -urow[s] : INF;
+            done[s] = !ok[s];
+        }
+        for (int step = 0; step < n; ++step) {
+            T lm = INF;
+            int lc = NONE;
+            for (int s = 0; s < K; ++s)
+                if (!done[s] && y[s] < lm) {
+                    lm = y[s];
+                    lc = c[s];
+                }
+            const T dmin = S::min(lm);
+            const int rr = S::imin(lm == dmin ? lc : NONE);
+            if (rr >= n) break;
+            const int cs = sc.aux[rr];
+            const T vcs = (T)sc.vb[cs];
+            for (int s = 0; s < K; ++s) {
+                done[s] = done[s] || (c[s] == rr);
+                const T nd = dmin + ((M[(ok[s] ? c[s] : 0) * n + cs] - urow[s]) - vcs);
+                if (!done[s] && nd < y[s]) y[s] = nd;
+            }
+        }
+        for (int s = 0; s < K; ++s)
+            if (!ok[s]) y[s] = 0;
+    }
+    T vc[K], ur[K];
+    for (int s = 0; s < K; ++s) {
+        vc[s] = v[s] + x[s];     // lane as columns
+        ur[s] = urow[s] + y[s];  // lane as rows
+    }
+    wave_sync();
+
+    if constexpr (sizeof(T) == 8) {
+        // ---- FP64: residual = mean of the residuals under the two points ----
+        for (int s = 0; s < K; ++s) {
+            sc.va[c[s]] = vc[s];
+            sc.vb[c[s]] = ur[s];
+        }
+        wave_sync();
+        T uc[K], vr[K];   // uc: lane as rows; vr: lane as columns
+        for (int s = 0; s < K; ++s) {
+            uc[s] = INF;
+            vr[s] = INF;
+            if (ok[s]) {
+                for (int q = 0; q < n; ++q) uc[s] = tmin(uc[s], M[c[s] * n + q] - (T)sc.va[q]);
+                for (int r = 0; r < n; ++r) vr[s] = tmin(vr[s], M[r * n + c[s]] - (T)sc.vb[r]);
+            }
+        }
+        wave_sync();
+        for (int s = 0; s < K; ++s) sc.va[c[s]] = uc[s];
+        wave_sync();
+        if (R != nullptr) {
+            for (int s = 0; s < K; ++s) {
+                if (!ok[s]) continue;
+                for (int r = 0; r < n; ++r) {
+                    const T m = M[r * n + c[s]];
+                    const T r1 = (m - vc[s]) - (T)sc.va[r];
+                    const T r2 = (m - (T)sc.vb[r]) - vr[s];
+                    R[r * n + c[s]] = (T)0.5 * (r1 + r2);
+                }
+            }
+        }
+        T suc = 0, svc = 0, sur = 0, svr = 0;
+        for (int s = 0; s < K; ++s) {
+            if (!ok[s]) continue;
+            if (duals != nullptr) {
+                duals[c[s]] = uc[s];
+                duals[n + c[s]] = vc[s];
+                duals[2 * n + c[s]] = ur[s];
+                duals[3 * n + c[s]] = vr[s];
+            }
+            if (assign != nullptr) assign[c[s]] = sg[s];
+            suc += uc[s];
+            svc += vc[s];
+            sur += ur[s];
+            svr += vr[s];
+        }
+        suc = S::sum(suc);
+        svc = S::sum(svc);
+        sur = S::sum(sur);
+        svr = S::sum(svr);
+        wave_sync();
+        return 0.5 * ((suc + svc) + (sur + svr));
+    } else {
+        // ---- FP32 certified: the duals are completed in FP64 rounding toward
+        // -inf, which keeps them feasible (u_r + v_q <= M_rq exactly).  With
+        // U = (uc + ur)/2 and V = (vc + vr)/2 the residual M - U - V (the same
+        // value as the mean of the two residuals) is then >= 0, and each entry
+        // and S = sum U + sum V are rounded down once.
+        for (int s = 0; s < K; ++s) {
+            sc.va[c[s]] = (double)vc[s];
+            sc.vb[c[s]] = (double)ur[s];
+        }
+        wave_sync();
+        double uc[K], vr[K], U[K], V[K];
+        for (int s = 0; s < K; ++s) {
+            uc[s] = __builtin_huge_val();
+            vr[s] = __builtin_huge_val();
+            if (ok[s]) {
+                for (int q = 0; q < n; ++q)
+                    uc[s] = __builtin_fmin(uc[s], sub_down((double)M[c[s] * n + q], sc.va[q]));
+                for (int r = 0; r < n; ++r)
+                    vr[s] = __builtin_fmin(vr[s], sub_down((double)M[r * n + c[s]], sc.vb[r]));
+            }
+            U[s] = ok[s] ? 0.5 * add_down(uc[s], (double)ur[s]) : 0.0;   // lane as rows
+            V[s] = ok[s] ? 0.5 * add_down((double)vc[s], vr[s]) : 0.0;   // lane as columns
+        }
+        wave_sync();
+        for (int s = 0; s < K; ++s) sc.va[c[s]] = U[s];
+        wave_sync();
+        if (R != nullptr) {
+            for (int s = 0; s < K; ++s) {
+                if (!ok[s]) continue;
+                for (int r = 0; r < n; ++r)
+                    R[r * n + c[s]] = to_float_down(sub_down(sub_down((double)M[r * n + c[s]], V[s]), sc.va[r]));
+            }
+        }
+        double su = 0.0, sv = 0.0;
+        for (int s = 0; s < K; ++s) {
+            if (!ok[s]) continue;
+            if (duals != nullptr) {
+                duals[c[s]] = (T)uc[s];
+                duals[n + c[s]] = vc[s];
+                duals[2 * n + c[s]] = ur[s];
+                duals[3 * n + c[s]] = (T)vr[s];
+            }
+            if (assign != nullptr) assign[c[s]] = sg[s];
+            su = add_down(su, U[s]);
+            sv = add_down(sv, V[s]);
+        }
+        su = S::sum_down(su);
+        sv = S::sum_down(sv);
+        wave_sync();
+        return add_down(su, sv);
+    }
+}
+
+}  // namespace qap

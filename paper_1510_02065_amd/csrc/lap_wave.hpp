@@ -25,9 +25,8 @@
 // With the solver's duals (u, v) and assignment sigma, v^c - v is the vector
 // of shortest distances in the column graph whose arc c -> q costs the reduced
 // cost M[sigma^-1(c)][q] - u - v >= 0, starting from label -v_q at every
-// column.  One dense Dijkstra pass over the columns computes it (a
-// Bellman-Ford variant in Jacobi rounds is kept for comparison).  The row point
-// is the same on the row graph.  Both
+// column.  One dense Dijkstra pass over the columns computes it.  The row
+// point is the same on the row graph.  Both
 // residual halves are >= 0 exactly: the subtracted dual is a row (column)
 // minimum of the already rounded differences.
 #pragma once
@@ -253,60 +252,6 @@ struct SegScratch {
     }
 };
 
-// Canonical point by dense Dijkstra over the columns (lanes = columns):
-// x_q = shortest distance to column q from label -v_q at every column, over
-// arcs c -> q of reduced cost M[p(c)][q] - u_{p(c)} - v_q >= 0.  Returns x.
-template <typename T, int SEG>
-__device__ __forceinline__ T col_dijkstra(const T* __restrict__ M, int n, int lane, bool ok, int col, int p,
-                                          T ucol, T v)
-{
-    using S = Seg<SEG>;
-    using Idx = typename S::Idx;
-    const T INF = inf_of<T>();
-    T dist = ok ? -v : INF;
-    bool done = !ok;
-    for (int s = 0; s < n; ++s) {
-        const T cand = done ? INF : dist;
-        const T dmin = S::min(cand);
-        const Idx cs_ = S::first(!done && cand == dmin);
-        const int c = S::mine(cs_);
-        if (c >= n) break;
-        const int r = S::bcast(p, cs_);
-        const T ur = S::bcast(ucol, cs_);
-        if (lane == c) done = true;
-        const T nd = dmin + ((M[r * n + col] - ur) - v);
-        if (!done && nd < dist) dist = nd;
-    }
-    return ok ? dist : (T)0;
-}
-
-// Row counterpart (lanes = rows): arcs s -> r of reduced cost
-// M[r][sigma(s)] - u_r - v_{sigma(s)}, from label -u_r.  Returns y.
-template <typename T, int SEG>
-__device__ __forceinline__ T row_dijkstra(const T* __restrict__ M, int n, int lane, bool ok, int row, int sig,
-                                          T urow, T v)
-{
-    using S = Seg<SEG>;
-    using Idx = typename S::Idx;
-    const T INF = inf_of<T>();
-    T dist = ok ? -urow : INF;
-    bool done = !ok;
-    for (int s = 0; s < n; ++s) {
-        const T cand = done ? INF : dist;
-        const T dmin = S::min(cand);
-        const Idx rs_ = S::first(!done && cand == dmin);
-        const int srow = S::mine(rs_);
-        if (srow >= n) break;
-        const Idx cs = S::at(sig, rs_);
-        const int csl = S::mine(cs);
-        const T vcs = S::bcast(v, cs);
-        if (lane == srow) done = true;
-        const T nd = dmin + ((M[row * n + csl] - urow) - vcs);
-        if (!done && nd < dist) dist = nd;
-    }
-    return ok ? dist : (T)0;
-}
-
 // Solve, canonicalise and write residuals for the n x n matrix sc.M (in LDS).
 //   n        problem size for this segment (0 <= n <= SEG; segment-uniform).
 //   sc       segment's LDS working set; sc.M (row stride n) is left unchanged.
@@ -315,20 +260,22 @@ __device__ __forceinline__ T row_dijkstra(const T* __restrict__ M, int n, int la
 //   assign   nullable; assign[r] = column of row r in the solver's assignment.
 // Returns S to every lane of the segment.  Must be called by whole waves
 // (every segment of the wave, possibly with different n).
-enum : int { kCanonDijkstra = 0, kCanonBellmanFord = 1 };
-
-template <typename T, int SEG, int CANON = kCanonDijkstra>
+template <typename T, int SEG>
 __device__ __forceinline__ double lap_concentrate_seg(const SegScratch<T, SEG>& sc, int n,
                                                       T* __restrict__ R, T* __restrict__ duals,
                                                       int32_t* __restrict__ assign)
 {
     using S = Seg<SEG>;
-    using Idx = typename S::Idx;
     const T* __restrict__ M = sc.M;
     const int lane = S::lane();
     const bool ok = lane < n;
     const int col = ok ? lane : 0;   // clamped column for lanes beyond n
     const T INF = inf_of<T>();
+    // During the solve the segment's scratch holds, per column lane j:
+    //   sc.sig[j] = p_j (row matched to column j, or -1), sc.va[j] = ucol_j
+    // (that row's dual), republished whenever they change, so a Dijkstra step
+    // fetches them for the chosen column with two LDS broadcast reads.
+    // sc.aux[r] marks rows that are already matched.
 
     // ---- column reduction -------------------------------------------------
     T v = 0;          // column dual (lane = column)
@@ -347,9 +294,11 @@ __device__ __forceinline__ double lap_concentrate_seg(const SegScratch<T, SEG>& 
     wave_sync();
     if (ok) atomicMin(&sc.aux[crow], lane);
     wave_sync();
-    // p: row matched to this column (or -1); ucol: that row's dual (0 here).
     int p = (ok && sc.aux[crow] == lane) ? crow : -1;
     T ucol = 0;
+    sc.sig[lane] = p;
+    sc.va[lane] = 0.0;
+    wave_sync();
 
     // ---- Hungarian method for the rows left free -----------------------------
     // Inserting free row i runs Dijkstra over columns with absolute tentative
@@ -378,20 +327,18 @@ __device__ __forceinline__ double lap_concentrate_seg(const SegScratch<T, SEG>& 
             }
             const T cand = live ? dist : INF;
             const T dmin = S::min(cand);
-            const Idx j1s = S::first(live && cand == dmin);
-            const int j1 = S::mine(j1s);
-            if (j1 >= n) break;   // no candidate: non-finite costs
-            const int pj = S::bcast(p, j1s);
-            const T uj = S::bcast(ucol, j1s);
+            const int j1 = S::mine(S::first(live && cand == dmin));
+            const int j1c = j1 < n ? j1 : 0;
+            const int pj = j1 < n ? sc.sig[j1c] : -1;
             if (pj < 0) {
-                jend = j1;
+                jend = j1 < n ? j1 : -1;   // no candidate: non-finite costs
                 dend = dmin;
                 break;
             }
             if (lane == j1) used = true;
             j0 = j1;
             i0 = pj;
-            ui0 = uj;
+            ui0 = (T)sc.va[j1c];
             d0 = dmin;
         }
         // Dual shift of the scanned tree.
@@ -414,52 +361,61 @@ __device__ __forceinline__ double lap_concentrate_seg(const SegScratch<T, SEG>& 
             p = (way >= 0) ? pw : i;
             ucol = (way >= 0) ? uw : dend;
         }
+        wave_sync();
+        sc.sig[lane] = p;
+        sc.va[lane] = (double)ucol;
+        wave_sync();
     }
 
-    // sigma (column of row r) for lane r, the solver's row dual u_r and the
-    // dual of the column matched to row r.
-    wave_sync();
-    if (ok && p >= 0 && p < n) sc.sig[p] = lane;
-    sc.aux[lane] = (ok && p >= 0) ? p : 0;
-    wave_sync();
-    const int sig = ok ? sc.sig[lane] : 0;
-    const T urow = S::read(ucol, sig);
-    const T vsig = S::read(v, sig);
+    // ---- column-canonical point (lanes = columns) ---------------------------
+    // x_q = shortest distance to column q from label -v_q at every column,
+    // over arcs c -> q of reduced cost M[p(c)][q] - u_{p(c)} - v_q >= 0.
+    T x;
+    {
+        T dist = ok ? -v : INF;
+        bool done = !ok;
+        for (int s = 0; s < n; ++s) {
+            const T cand = done ? INF : dist;
+            const T dmin = S::min(cand);
+            const int c = S::mine(S::first(!done && cand == dmin));
+            if (c >= n) break;
+            const int r = sc.sig[c];
+            const T ur = (T)sc.va[c];
+            if (lane == c) done = true;
+            const T nd = dmin + ((M[r * n + col] - ur) - v);
+            if (!done && nd < dist) dist = nd;
+        }
+        x = ok ? dist : (T)0;
+    }
 
-    // ---- canonical points ------------------------------------------------------
-    T x, y;
-    if constexpr (CANON == kCanonDijkstra) {
-        x = col_dijkstra<T, SEG>(M, n, lane, ok, col, p, ucol, v);
-        y = row_dijkstra<T, SEG>(M, n, lane, ok, col, sig, urow, v);
-    } else {
-        // Bellman-Ford in Jacobi rounds.  Columns:
-        // x_q <- min(x_q, min_c (x_c - u_{p(c)}) + M[p(c)][q] - v_q), from x = -v.
-        x = ok ? -v : (T)0;
-        for (int round = 0; round < SEG; ++round) {
-            sc.va[lane] = ok ? (double)(x - ucol) : 0.0;
-            wave_sync();
-            T best = INF;
-            for (int c = 0; c < n; ++c) best = tmin(best, (T)sc.va[c] + M[sc.aux[c] * n + col]);
-            const T cand = best - v;
-            const bool ch = ok && cand < x;
-            if (ch) x = cand;
-            wave_sync();
-            if (__ballot(ch) == 0ull) break;
+    // sigma (column of row r, lane r) in sc.aux, v in sc.vb; the solver's row
+    // dual u_r = ucol at column sigma(r).
+    wave_sync();
+    if (ok && p >= 0) sc.aux[p] = lane;
+    sc.vb[lane] = (double)v;
+    wave_sync();
+    const int sig = ok ? sc.aux[lane] : 0;
+    const T urow = (T)sc.va[sig];
+
+    // ---- row-canonical point (lanes = rows) ---------------------------------
+    // y_r = shortest distance to row r from label -u_r at every row, over
+    // arcs s -> r of reduced cost M[r][sigma(s)] - u_r - v_{sigma(s)} >= 0.
+    T y;
+    {
+        T dist = ok ? -urow : INF;
+        bool done = !ok;
+        for (int s = 0; s < n; ++s) {
+            const T cand = done ? INF : dist;
+            const T dmin = S::min(cand);
+            const int srow = S::mine(S::first(!done && cand == dmin));
+            if (srow >= n) break;
+            const int cs = sc.aux[srow];
+            const T vcs = (T)sc.vb[cs];
+            if (lane == srow) done = true;
+            const T nd = dmin + ((M[col * n + cs] - urow) - vcs);
+            if (!done && nd < dist) dist = nd;
         }
-        // Rows: y_r <- min(y_r, min_s (y_s - v_{sigma(s)}) + M[r][sigma(s)] - u_r), from y = -u.
-        sc.aux[lane] = sig;
-        y = ok ? -urow : (T)0;
-        for (int round = 0; round < SEG; ++round) {
-            sc.vb[lane] = ok ? (double)(y - vsig) : 0.0;
-            wave_sync();
-            T best = INF;
-            for (int s2 = 0; s2 < n; ++s2) best = tmin(best, (T)sc.vb[s2] + M[col * n + sc.aux[s2]]);
-            const T cand = best - urow;
-            const bool ch = ok && cand < y;
-            if (ch) y = cand;
-            wave_sync();
-            if (__ballot(ch) == 0ull) break;
-        }
+        y = ok ? dist : (T)0;
     }
     const T vc = v + x;
     const T ur = urow + y;

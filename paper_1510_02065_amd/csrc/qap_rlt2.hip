@@ -48,7 +48,10 @@ constexpr long long kTraceCap = 1024;
 
 // Instances of one family that share a segment size.
 struct ClassHost {
-    int seg = 0;
+    int seg = 0;       // size bucket: next power of two >= n (8 at least)
+    int seg_run = 0;   // lanes per problem, chosen by the tuner
+    int k_run = 0;     // columns per lane (seg_run * k_run >= nmax)
+    int wpb = 1;
     int nmax = 0;
     std::vector<int> ids;
     std::vector<long long> pre;
@@ -72,6 +75,10 @@ struct qap_rlt2 {
     bool own_stream = false;
     int trace_level = 1;
     int use_graph = 1;
+    int autotune = 1;
+    bool tuned = false;
+    size_t lds_limit = 65536;   // dynamic LDS a workgroup may request
+    std::string tune_cache;
     size_t elem = 8;   // bytes per reduced cost
     std::vector<qap::Inst> inst;
     long long totalB = 0, totalC = 0, totalD = 0, totalWG = 0;
@@ -104,24 +111,65 @@ namespace {
 
 // ---- launches ---------------------------------------------------------------
 
-template <typename T, int SEG>
-hipError_t launch_family_seg(qap_rlt2* h, int famk, const ClassHost& c, double* values)
+hipError_t enqueue_step_any(qap_rlt2* h, int step);
+
+// (lanes per problem, columns per lane) configurations of the concentration
+// kernels; for a problem size n the candidates are (SEG, ceil(n/SEG)).
+bool slot_cfg_allowed(int seg, int k)
 {
-    if (c.total <= 0) return hipSuccess;
+    switch (seg) {
+    case 8: return (k >= 1 && k <= 6) || k == 8;
+    case 16: return k >= 1 && k <= 4;
+    case 32: return k >= 1 && k <= 2;
+    case 64: return k == 1;
+    default: return false;
+    }
+}
+
+template <typename T, int SEG, int K>
+size_t slot_lds(int nmax) { return (size_t)(64 / SEG) * qap::SlotLds<T, SEG, K>::bytes(nmax); }
+
+template <typename T>
+size_t slot_lds_any(int seg, int k, int nmax)
+{
+#define QAP_CFG(SG, KK) \
+    if (seg == SG && k == KK) return slot_lds<T, SG, KK>(nmax);
+    QAP_CFG(8, 1) QAP_CFG(8, 2) QAP_CFG(8, 3) QAP_CFG(8, 4) QAP_CFG(8, 5) QAP_CFG(8, 6) QAP_CFG(8, 8)
+    QAP_CFG(16, 1) QAP_CFG(16, 2) QAP_CFG(16, 3) QAP_CFG(16, 4) QAP_CFG(32, 1) QAP_CFG(32, 2) QAP_CFG(64, 1)
+#undef QAP_CFG
+    return (size_t)-1;
+}
+
+template <typename T, int SEG, int K>
+hipError_t launch_family_sk(qap_rlt2* h, int famk, const ClassHost& c, qap::FamilyClass fc, double* values)
+{
+    if (fc.total <= 0) return hipSuccess;
     constexpr int LPW = 64 / SEG;
-    constexpr int WPB = 1;
-    const size_t lds = (size_t)WPB * LPW * qap::SegLds<T, SEG>::bytes(c.nmax);
-    const unsigned grid = (unsigned)((c.total + (long long)WPB * LPW - 1) / ((long long)WPB * LPW));
+    const size_t lds = slot_lds<T, SEG, K>(c.nmax);
+    if (lds > h->lds_limit) return hipErrorInvalidConfiguration;   // not launched
+    const unsigned grid = (unsigned)((fc.total + LPW - 1) / LPW);
     T* D = static_cast<T*>(h->dD);
     T* C = static_cast<T*>(h->dC);
     T* B = static_cast<T*>(h->dB);
     if (famk == qap::kFamD)
-        hipLaunchKernelGGL((qap::k_lap_family<T, SEG, WPB, qap::kFamD>), dim3(grid), dim3(64 * WPB), lds,
-                           h->stream, D, C, B, h->dInst, c.dev(), c.nmax, values);
+        hipLaunchKernelGGL((qap::k_lap_family_s<T, SEG, K, qap::kFamD>), dim3(grid), dim3(64), lds, h->stream, D, C,
+                           B, h->dInst, fc, c.nmax, values);
     else
-        hipLaunchKernelGGL((qap::k_lap_family<T, SEG, WPB, qap::kFamC>), dim3(grid), dim3(64 * WPB), lds,
-                           h->stream, D, C, B, h->dInst, c.dev(), c.nmax, values);
+        hipLaunchKernelGGL((qap::k_lap_family_s<T, SEG, K, qap::kFamC>), dim3(grid), dim3(64), lds, h->stream, D, C,
+                           B, h->dInst, fc, c.nmax, values);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_family_class(qap_rlt2* h, int famk, const ClassHost& c, qap::FamilyClass fc, int seg, int k,
+                               double* values)
+{
+#define QAP_CFG(SG, KK) \
+    if (seg == SG && k == KK) return launch_family_sk<T, SG, KK>(h, famk, c, fc, values);
+    QAP_CFG(8, 1) QAP_CFG(8, 2) QAP_CFG(8, 3) QAP_CFG(8, 4) QAP_CFG(8, 5) QAP_CFG(8, 6) QAP_CFG(8, 8)
+    QAP_CFG(16, 1) QAP_CFG(16, 2) QAP_CFG(16, 3) QAP_CFG(16, 4) QAP_CFG(32, 1) QAP_CFG(32, 2) QAP_CFG(64, 1)
+#undef QAP_CFG
+    return hipErrorInvalidConfiguration;
 }
 
 template <typename T>
@@ -129,26 +177,202 @@ hipError_t launch_family(qap_rlt2* h, int famk, double* values)
 {
     for (const ClassHost& c : h->fam[famk]) {
         if (c.total <= 0) continue;
-        hipError_t e;
-        switch (c.seg) {
-        case 8: e = launch_family_seg<T, 8>(h, famk, c, values); break;
-        case 16: e = launch_family_seg<T, 16>(h, famk, c, values); break;
-        case 32: e = launch_family_seg<T, 32>(h, famk, c, values); break;
-        default: e = launch_family_seg<T, 64>(h, famk, c, values); break;
-        }
+        hipError_t e = launch_family_class<T>(h, famk, c, c.dev(), c.seg_run, c.k_run, values);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-template <typename T, int SEG>
-hipError_t launch_B_seg(qap_rlt2* h, const ClassHost& c)
+// ---- autotuner ----------------------------------------------------------------
+// For each class of a family, time every (lanes per problem, columns per
+// lane) candidate on the first min(total, kTuneItems) problems of the class,
+// each run starting from the same saved copy of the blocks and parents those
+// problems touch, and keep the fastest.  The choice does not change the
+// algorithm's decisions (ties go to the lowest column either way); it changes
+// only the order of the final sums, by rounding.
+constexpr long long kTuneItems = 16384;
+
+std::string tune_key(const qap_rlt2* h, int famk, const ClassHost& c)
+{
+    char buf[128];
+    snprintf(buf, sizeof(buf), "gfx950 prec=%d fam=%d seg=%d nmax=%d", h->precision, famk, c.seg, c.nmax);
+    return buf;
+}
+
+void load_tune_cache(qap_rlt2* h)
+{
+    if (h->tune_cache.empty()) return;
+    FILE* f = fopen(h->tune_cache.c_str(), "r");
+    if (!f) return;
+    std::map<std::string, std::pair<int, int>> m;
+    char line[256];
+    while (fgets(line, sizeof(line), f)) {
+        char* bar = strchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        int seg = 0, wpb = 0;
+        if (sscanf(bar + 1, "%d %d", &seg, &wpb) == 2) m[line] = {seg, wpb};
+    }
+    fclose(f);
+    int hits = 0, need = 0;
+    for (int famk = 0; famk < 2; ++famk)
+        for (ClassHost& c : h->fam[famk]) {
+            if (c.total <= 0) continue;
+            ++need;
+            auto it = m.find(tune_key(h, famk, c));
+            if (it != m.end() && slot_cfg_allowed(it->second.first, it->second.second) &&
+                it->second.first * it->second.second >= c.nmax) {
+                c.seg_run = it->second.first;
+                c.k_run = it->second.second;
+                ++hits;
+            }
+        }
+    if (need > 0 && hits == need) h->tuned = true;
+}
+
+void save_tune_cache(const qap_rlt2* h)
+{
+    if (h->tune_cache.empty()) return;
+    std::map<std::string, std::pair<int, int>> m;
+    if (FILE* f = fopen(h->tune_cache.c_str(), "r")) {
+        char line[256];
+        while (fgets(line, sizeof(line), f)) {
+            char* bar = strchr(line, '|');
+            if (!bar) continue;
+            *bar = 0;
+            int seg = 0, wpb = 0;
+            if (sscanf(bar + 1, "%d %d", &seg, &wpb) == 2) m[line] = {seg, wpb};
+        }
+        fclose(f);
+    }
+    for (int famk = 0; famk < 2; ++famk)
+        for (const ClassHost& c : h->fam[famk])
+            if (c.total > 0) m[tune_key(h, famk, c)] = {c.seg_run, c.k_run};
+    if (FILE* f = fopen(h->tune_cache.c_str(), "w")) {
+        for (auto& kv : m) fprintf(f, "%s|%d %d\n", kv.first.c_str(), kv.second.first, kv.second.second);
+        fclose(f);
+    }
+}
+
+template <typename T>
+hipError_t tune_family(qap_rlt2* h, int famk)
+{
+    hipError_t e = hipSuccess;
+    for (ClassHost& c : h->fam[famk]) {
+        if (c.total <= 0) continue;
+        const long long X = std::min(c.total, kTuneItems);
+        // Element ranges touched by the first X problems: blocks and parents.
+        int kk = 0;
+        while (kk + 1 < (int)c.pre.size() && c.pre[kk + 1] <= X - 1) ++kk;
+        const qap::Inst& I0 = h->inst[c.ids[0]];
+        const qap::Inst& IL = h->inst[c.ids[kk]];
+        const long long bl = X - 1 - c.pre[kk];
+        long long blk0, blk1, par0, par1;
+        char* blkbase;
+        char* parbase;
+        if (famk == qap::kFamD) {
+            blk0 = I0.offD;
+            blk1 = IL.offD + (bl + 1) * IL.ldD;
+            par0 = I0.offC;
+            par1 = IL.offC + bl + 1;
+            blkbase = static_cast<char*>(h->dD);
+            parbase = static_cast<char*>(h->dC);
+        } else {
+            blk0 = I0.offC;
+            blk1 = IL.offC + (bl + 1) * (long long)(IL.N - 1) * (IL.N - 1);
+            par0 = I0.offB;
+            par1 = IL.offB + bl + 1;
+            blkbase = static_cast<char*>(h->dC);
+            parbase = static_cast<char*>(h->dB);
+        }
+        const size_t bbytes = (size_t)(blk1 - blk0) * h->elem, pbytes = (size_t)(par1 - par0) * h->elem;
+        void* sblk = nullptr;
+        void* spar = nullptr;
+        if ((e = hipMalloc(&sblk, bbytes)) != hipSuccess) return e;
+        if ((e = hipMalloc(&spar, pbytes)) != hipSuccess) {
+            (void)hipFree(sblk);
+            return e;
+        }
+        char* b0 = blkbase + blk0 * h->elem;
+        char* p0 = parbase + par0 * h->elem;
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        auto cleanup = [&]() {
+            if (ev0) (void)hipEventDestroy(ev0);
+            if (ev1) (void)hipEventDestroy(ev1);
+            (void)hipFree(sblk);
+            (void)hipFree(spar);
+        };
+        if ((e = hipMemcpyAsync(sblk, b0, bbytes, hipMemcpyDeviceToDevice, h->stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(spar, p0, pbytes, hipMemcpyDeviceToDevice, h->stream)) != hipSuccess ||
+            (e = hipEventCreate(&ev0)) != hipSuccess || (e = hipEventCreate(&ev1)) != hipSuccess) {
+            cleanup();
+            return e;
+        }
+        qap::FamilyClass fc = c.dev();
+        fc.total = X;
+        float best = 1e30f;
+        int best_seg = c.seg_run, best_k = c.k_run;
+        for (int seg : {8, 16, 32, 64}) {
+            const int k = (c.nmax + seg - 1) / seg;
+            if (!slot_cfg_allowed(seg, k)) continue;
+            if (slot_lds_any<T>(seg, k, c.nmax) > h->lds_limit) continue;
+            float ms = 0.f;
+            for (int rep = 0; rep < 2; ++rep) {
+                if ((e = hipMemcpyAsync(b0, sblk, bbytes, hipMemcpyDeviceToDevice, h->stream)) != hipSuccess ||
+                    (e = hipMemcpyAsync(p0, spar, pbytes, hipMemcpyDeviceToDevice, h->stream)) != hipSuccess ||
+                    (e = hipEventRecord(ev0, h->stream)) != hipSuccess ||
+                    (e = launch_family_class<T>(h, famk, c, fc, seg, k, nullptr)) != hipSuccess ||
+                    (e = hipEventRecord(ev1, h->stream)) != hipSuccess ||
+                    (e = hipEventSynchronize(ev1)) != hipSuccess ||
+                    (e = hipEventElapsedTime(&ms, ev0, ev1)) != hipSuccess) {
+                    cleanup();
+                    return e;
+                }
+            }
+            if (ms < best) {
+                best = ms;
+                best_seg = seg;
+                best_k = k;
+            }
+        }
+        c.seg_run = best_seg;
+        c.k_run = best_k;
+        e = hipMemcpyAsync(b0, sblk, bbytes, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(p0, spar, pbytes, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        cleanup();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// First iteration of a handle with autotuning: run the steps one by one and
+// tune each concentration family on its live data just before it runs.
+hipError_t tuned_first_iteration(qap_rlt2* h)
+{
+    const bool f64 = h->precision == QAP_FP64;
+    hipError_t e;
+    if ((e = enqueue_step_any(h, 3)) != hipSuccess) return e;
+    if ((e = f64 ? tune_family<double>(h, qap::kFamD) : tune_family<float>(h, qap::kFamD)) != hipSuccess) return e;
+    if ((e = enqueue_step_any(h, 4)) != hipSuccess) return e;
+    if ((e = enqueue_step_any(h, 5)) != hipSuccess) return e;
+    if ((e = f64 ? tune_family<double>(h, qap::kFamC) : tune_family<float>(h, qap::kFamC)) != hipSuccess) return e;
+    if ((e = enqueue_step_any(h, 6)) != hipSuccess) return e;
+    if ((e = enqueue_step_any(h, 7)) != hipSuccess) return e;
+    h->tuned = true;
+    save_tune_cache(h);
+    return hipSuccess;
+}
+
+template <typename T, int SEG, int K>
+hipError_t launch_B_sk(qap_rlt2* h, const ClassHost& c)
 {
     constexpr int LPW = 64 / SEG;
-    const size_t lds = LPW * qap::SegLds<T, SEG>::bytes(c.nmax);
+    const size_t lds = slot_lds<T, SEG, K>(c.nmax);
+    if (lds > h->lds_limit) return hipErrorInvalidConfiguration;
     const unsigned grid = (unsigned)((c.total + LPW - 1) / LPW);
     const bool tr = h->trace_level >= 1;
-    hipLaunchKernelGGL((qap::k_lap_B<T, SEG>), dim3(grid), dim3(64), lds, h->stream, static_cast<T*>(h->dB),
+    hipLaunchKernelGGL((qap::k_lap_B_s<T, SEG, K>), dim3(grid), dim3(64), lds, h->stream, static_cast<T*>(h->dB),
                        h->dInst, c.dev(), c.nmax, h->dLB, tr ? h->dTrace : nullptr, tr ? h->dCounter : nullptr,
                        kTraceCap, h->trace_level >= 2 ? h->dValB : nullptr);
     return hipGetLastError();
@@ -159,13 +383,14 @@ hipError_t launch_B(qap_rlt2* h)
 {
     for (const ClassHost& c : h->fam[2]) {
         if (c.total <= 0) continue;
-        hipError_t e;
-        switch (c.seg) {
-        case 8: e = launch_B_seg<T, 8>(h, c); break;
-        case 16: e = launch_B_seg<T, 16>(h, c); break;
-        case 32: e = launch_B_seg<T, 32>(h, c); break;
-        default: e = launch_B_seg<T, 64>(h, c); break;
+        hipError_t e = hipErrorInvalidConfiguration;
+#define QAP_CFG(SG, KK) \
+    else if (c.seg_run == SG && c.k_run == KK) e = launch_B_sk<T, SG, KK>(h, c);
+        if (false) {
         }
+        QAP_CFG(8, 1) QAP_CFG(8, 2) QAP_CFG(8, 3) QAP_CFG(8, 4) QAP_CFG(8, 5) QAP_CFG(8, 6) QAP_CFG(8, 8)
+        QAP_CFG(16, 1) QAP_CFG(16, 2) QAP_CFG(16, 3) QAP_CFG(16, 4) QAP_CFG(32, 1) QAP_CFG(32, 2) QAP_CFG(64, 1)
+#undef QAP_CFG
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -342,6 +567,8 @@ qap_status qap_rlt2_default_opts(qap_rlt2_opts* o)
     o->stream = nullptr;
     o->trace_level = 1;
     o->use_graph = 1;
+    o->autotune = 1;
+    o->tune_cache = nullptr;
     return QAP_OK;
 }
 
@@ -391,6 +618,8 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
     h->precision = o.precision;
     h->trace_level = std::max(0, std::min(2, o.trace_level));
     h->use_graph = o.use_graph ? 1 : 0;
+    h->autotune = o.autotune ? 1 : 0;
+    if (o.tune_cache) h->tune_cache = o.tune_cache;
     h->elem = o.precision == QAP_FP64 ? sizeof(double) : sizeof(float);
     h->tLB.resize(count);
     h->tLBp.resize(count);
@@ -470,6 +699,29 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
         }
     }
 
+    // LDS a workgroup may request, and the default configuration of every
+    // class: the most problems per wave that fit.
+    {
+        int lim = 0;
+        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && lim > 0)
+            h->lds_limit = (size_t)lim;
+    }
+    for (auto& f : h->fam)
+        for (ClassHost& c : f) {
+            if (c.total <= 0) continue;
+            for (int seg : {8, 16, 32, 64}) {
+                const int k = (c.nmax + seg - 1) / seg;
+                if (!slot_cfg_allowed(seg, k)) continue;
+                const size_t need = h->precision == QAP_FP64 ? slot_lds_any<double>(seg, k, c.nmax)
+                                                             : slot_lds_any<float>(seg, k, c.nmax);
+                if (need > h->lds_limit) continue;
+                c.seg_run = seg;
+                c.k_run = k;
+                break;
+            }
+            if (c.seg_run == 0) return bail(fail(QAP_EINVAL, "problem size needs more LDS than a workgroup has"));
+        }
+
     const size_t bytesD = (size_t)h->totalD * h->elem;
     size_t freeb = 0, totalb = 0;
     CK(hipMemGetInfo(&freeb, &totalb));
@@ -502,6 +754,7 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
             CK(upload(&c.d_ids, c.ids, h->stream));
             CK(upload(&c.d_pre, c.pre, h->stream));
         }
+    if (h->autotune) load_tune_cache(h);
     std::vector<double> lb0(2 * count, 0.0);
     for (int k = 0; k < count; ++k) lb0[2 * k] = constants ? constants[k] : 0.0;
     CK(hipMemcpyAsync(h->dLB, lb0.data(), lb0.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
@@ -558,6 +811,19 @@ qap_status qap_rlt2_ascend(qap_rlt2* h, int iters, double* bound)
     if (st != QAP_OK) return st;
     if (iters < 0) return fail(QAP_EINVAL, "iters must be >= 0");
     int left = iters;
+    if (left > 0 && h->autotune && !h->tuned) {
+        hipError_t e = tuned_first_iteration(h);
+        if (e != hipSuccess) return mark_broken(h, e, "autotuned first iteration");
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return mark_broken(h, e, "hipStreamSynchronize");
+        h->iterations += 1;
+        st = drain_trace(h);
+        if (st != QAP_OK) {
+            h->broken = true;
+            return st;
+        }
+        --left;
+    }
     while (left > 0) {
         const int chunk = (int)std::min<long long>(left, kTraceCap);
         if (h->use_graph) {
