@@ -860,7 +860,8 @@ qap_status qap_rlt2_ascend(qap_rlt2* h, int iters, double* bound)
     if (bound) {
         if (h->precision == QAP_FP64) {
             double lb[2];
-            hipError_t e = hipMemcpy(lb, h->dLB, sizeof(lb), hipMemcpyDeviceToHost);
+            hipError_t e = hipStreamSynchronize(h->stream);
+            if (e == hipSuccess) e = hipMemcpy(lb, h->dLB, sizeof(lb), hipMemcpyDeviceToHost);
             if (e != hipSuccess) return mark_broken(h, e, "hipMemcpy");
             *bound = lb[0];
         } else {
@@ -878,9 +879,9 @@ qap_status qap_rlt2_step(qap_rlt2* h, int step)
         return fail(QAP_EINVAL, "step must be 3 (steps 1-3), 4, 5, 6 or 7 (steps 7-8)");
     hipError_t e = enqueue_step_any(h, step);
     if (e != hipSuccess) return mark_broken(h, e, "kernel launch");
-    e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return mark_broken(h, e, "hipStreamSynchronize");
     if (step == 7) {
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return mark_broken(h, e, "hipStreamSynchronize");
         h->iterations += 1;
         st = drain_trace(h);
         if (st != QAP_OK) return st;
@@ -936,7 +937,8 @@ qap_status qap_rlt2_bound(qap_rlt2* h, double* lb, int64_t* iterations)
     if (st != QAP_OK) return st;
     if (lb) {
         double v[2];
-        hipError_t e = hipMemcpy(v, h->dLB, sizeof(v), hipMemcpyDeviceToHost);
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e == hipSuccess) e = hipMemcpy(v, h->dLB, sizeof(v), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return mark_broken(h, e, "hipMemcpy");
         *lb = v[0];
     }
@@ -971,6 +973,7 @@ qap_status qap_rlt2_instance_lap_values(qap_rlt2* h, int k, double* sD, double* 
     if (h->trace_level < 2) return fail(QAP_EINVAL, "per-assignment values need trace_level 2");
     const qap::Inst& I = h->inst[k];
     const long long nC = (long long)I.N * I.N * (I.N - 1) * (I.N - 1);
+    QAP_HIP(hipStreamSynchronize(h->stream));
     if (sD) QAP_HIP(hipMemcpy(sD, h->dValD + I.offC, nC * sizeof(double), hipMemcpyDeviceToHost));
     if (sC) QAP_HIP(hipMemcpy(sC, h->dValC + I.offB, (size_t)I.N * I.N * sizeof(double), hipMemcpyDeviceToHost));
     if (sB) QAP_HIP(hipMemcpy(sB, h->dValB + k, sizeof(double), hipMemcpyDeviceToHost));
