@@ -70,19 +70,26 @@ typedef struct {
                          graph per iteration; 0: plain launches                */
     int autotune;     /* 1 (default): during the first qap_rlt2_ascend, time the
                          concentration kernels of every family and size class
-                         over the problems per wave (segment of n..64 lanes)
-                         and the waves per workgroup (1, 2, 4), on a restored
-                         copy of the live data, and keep the fastest; the
-                         results do not depend on the choice.  0: natural
-                         segment, one wave per workgroup                      */
+                         over the lanes per problem (8, 16, 32 or 64, with as
+                         many columns per lane as the size needs) on a
+                         restored copy of the live data, and keep the fastest;
+                         the algorithm's decisions do not depend on the
+                         choice, only the rounding of its final sums.  0: the
+                         configuration with the most problems per wave that
+                         fits in LDS                                          */
     const char* tune_cache; /* nullable path of a text file that stores the
                          tuned choices and is read back by later handles     */
+    int complementary; /* 1 (default): concentrate each pair of complementary
+                         D blocks D_ijkn, D_knij (Section 6) once and write the
+                         residual and S to both: after the six-way transfer of
+                         step 3 the two blocks are equal, so the state is bit
+                         for bit that of 0, which concentrates every block    */
 } qap_rlt2_opts;
 
 typedef struct qap_rlt2 qap_rlt2;
 
 /* Fill *opts with the defaults (FP64, current device, own stream,
- * trace_level 1, use_graph 1, autotune 1, no tune cache). */
+ * trace_level 1, use_graph 1, autotune 1, no tune cache, complementary 1). */
 qap_status qap_rlt2_default_opts(qap_rlt2_opts* opts);
 
 /* Create a dual-ascent state for the QAP of equation (1) with flows F and

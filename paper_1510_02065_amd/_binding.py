@@ -27,7 +27,7 @@ _vp = ctypes.c_void_p
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("trace_level", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("tune_cache", ctypes.c_char_p)]
+                ("tune_cache", ctypes.c_char_p), ("complementary", ctypes.c_int)]
 
 
 SIGNATURES = {
@@ -103,7 +103,8 @@ def _dptr(a):
     return None if a is None else a.ctypes.data_as(_dp)
 
 
-def _opts(precision, trace_level, use_graph, device, stream, autotune=True, tune_cache=None):
+def _opts(precision, trace_level, use_graph, device, stream, autotune=True, tune_cache=None,
+          complementary=True):
     opts = Opts()
     _check(lib().qap_rlt2_default_opts(ctypes.byref(opts)), "qap_rlt2_default_opts")
     opts.precision = {"fp64": QAP_FP64, "fp32": QAP_FP32_CERTIFIED}[precision]
@@ -113,6 +114,7 @@ def _opts(precision, trace_level, use_graph, device, stream, autotune=True, tune
     opts.use_graph = 1 if use_graph else 0
     opts.autotune = 1 if autotune else 0
     opts.tune_cache = None if tune_cache is None else str(tune_cache).encode()
+    opts.complementary = 1 if complementary else 0
     return opts
 
 
@@ -122,7 +124,8 @@ class Rlt2:
     refer to instance 0 and the *_k accessors to instance k."""
 
     def __init__(self, F, D, B0=None, constant=0.0, precision="fp64", trace_level=1,
-                 use_graph=True, device=-1, stream=None, autotune=True, tune_cache=None):
+                 use_graph=True, device=-1, stream=None, autotune=True, tune_cache=None,
+                 complementary=True):
         L = lib()
         F = _f64(F)
         D = _f64(D)
@@ -130,7 +133,7 @@ class Rlt2:
         if F.shape != (N, N) or D.shape != (N, N):
             raise ValueError("F and D must be square and of the same size")
         B0 = None if B0 is None else _f64(B0)
-        opts = _opts(precision, trace_level, use_graph, device, stream, autotune, tune_cache)
+        opts = _opts(precision, trace_level, use_graph, device, stream, autotune, tune_cache, complementary)
         h = _vp()
         _check(L.qap_rlt2_create_ex(N, _dptr(F), _dptr(D), _dptr(B0), float(constant),
                                     ctypes.byref(opts), ctypes.byref(h)), "qap_rlt2_create_ex")
@@ -141,7 +144,8 @@ class Rlt2:
 
     @classmethod
     def batch(cls, Fs, Ds, B0s=None, constants=None, precision="fp64", trace_level=1,
-              use_graph=True, device=-1, stream=None, autotune=True, tune_cache=None):
+              use_graph=True, device=-1, stream=None, autotune=True, tune_cache=None,
+              complementary=True):
         """Many instances (e.g. branch-and-bound nodes) in one handle."""
         K = len(Fs)
         Fs = [_f64(F) for F in Fs]
@@ -152,7 +156,7 @@ class Rlt2:
         fp = (ctypes.c_void_p * K)(*[F.ctypes.data for F in Fs])
         dp = (ctypes.c_void_p * K)(*[D.ctypes.data for D in Ds])
         bp = (ctypes.c_void_p * K)(*[None if B is None else B.ctypes.data for B in B0s])
-        opts = _opts(precision, trace_level, use_graph, device, stream, autotune, tune_cache)
+        opts = _opts(precision, trace_level, use_graph, device, stream, autotune, tune_cache, complementary)
         h = _vp()
         _check(lib().qap_rlt2_batch_create(K, Ns.ctypes.data, ctypes.cast(fp, _vp), ctypes.cast(dp, _vp),
                                            ctypes.cast(bp, _vp), consts.ctypes.data, ctypes.byref(opts),

@@ -21,60 +21,22 @@ struct FamilyClass {
 
 enum : int { kFamD = 0, kFamC = 1 };
 
-// D -> C (fam kFamD: blocks D_beta of size N-2, parent c_beta) or C -> B
-// (kFamC: blocks C_ij of size N-1, parent b_ij).  parent += S, the block is
-// replaced by its residual, values[...] = S when values is not null (values
-// are packed like the parents).
-template <typename T, int SEG, int WPB, int FAM>
-__global__ __launch_bounds__(64 * WPB) void k_lap_family(T* __restrict__ D, T* __restrict__ C,
-                                                         T* __restrict__ B, const Inst* __restrict__ inst,
-                                                         FamilyClass fc, int nmax,
-                                                         double* __restrict__ values)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int LPW = 64 / SEG;
-    const int wave = threadIdx.x >> 6;
-    const int seg = (threadIdx.x & 63) / SEG;
-    const int lane = threadIdx.x & (SEG - 1);
-    const long long x = ((long long)blockIdx.x * WPB + wave) * LPW + seg;
-    const bool active = x < fc.total;
-    int n = 0;
-    T* blk = nullptr;
-    long long pidx = 0;
-    if (active) {
-        const int kk = find_seg(fc.pre, fc.Kc, x);
-        const Inst I = inst[fc.cls[kk]];
-        const long long b = x - fc.pre[kk];
-        if (FAM == kFamD) {
-            n = I.N - 2;
-            blk = D + I.offD + b * I.ldD;
-            pidx = I.offC + b;
-        } else {
-            n = I.N - 1;
-            blk = C + I.offC + b * (long long)(I.N - 1) * (I.N - 1);
-            pidx = I.offB + b;
-        }
-    }
-    const SegScratch<T, SEG> sc(smem + (wave * LPW + seg) * SegLds<T, SEG>::bytes(nmax), n);
-    for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
-    wave_sync();
-    const double S = lap_concentrate_seg<T, SEG>(sc, n, active ? blk : nullptr, nullptr, nullptr);
-    if (active && lane == 0) {
-        T* parent = (FAM == kFamD) ? C : B;
-        if constexpr (sizeof(T) == 8)
-            parent[pidx] = parent[pidx] + S;
-        else
-            parent[pidx] = to_float_down(add_down((double)parent[pidx], S));
-        if (values) values[pidx] = S;
-    }
-}
+// How the D family is enumerated (see half_block).
+enum : int {
+    kAllBlocks = 0,    // problem b is block b
+    kHalfNoTwin = 1,   // problem b is half block b; the complement is not written
+    kHalfTwin = 2,     // problem b is half block b; residual and S also go to the complement
+};
 
-// Same as k_lap_family with K columns per lane (lap_concentrate_slots):
-// 64/SEG problems per wave, one wave per workgroup.
+// D -> C (FAM kFamD: blocks D_beta of size N-2, parent c_beta) or C -> B
+// (kFamC: blocks C_ij of size N-1, parent b_ij), K columns per lane, 64/SEG
+// problems per wave, one wave per workgroup.  parent += S, the block is
+// replaced by its residual, values[...] = S when values is not null (values
+// are packed like the parents).  `mode` applies to the D family only.
 template <typename T, int SEG, int K, int FAM>
 __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __restrict__ C, T* __restrict__ B,
                                                      const Inst* __restrict__ inst, FamilyClass fc, int nmax,
-                                                     double* __restrict__ values)
+                                                     double* __restrict__ values, int mode)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int LPW = 64 / SEG;
@@ -84,15 +46,22 @@ __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __res
     const bool active = x < fc.total;
     int n = 0;
     T* blk = nullptr;
-    long long pidx = 0;
+    T* twin = nullptr;
+    long long pidx = 0, pidx2 = -1;
     if (active) {
         const int kk = find_seg(fc.pre, fc.Kc, x);
         const Inst I = inst[fc.cls[kk]];
         const long long b = x - fc.pre[kk];
         if (FAM == kFamD) {
             n = I.N - 2;
-            blk = D + I.offD + b * I.ldD;
-            pidx = I.offC + b;
+            long long beta = b, tb = -1;
+            if (mode != kAllBlocks) half_block(I.N, b, &beta, &tb);
+            blk = D + I.offD + beta * I.ldD;
+            pidx = I.offC + beta;
+            if (mode == kHalfTwin) {
+                twin = D + I.offD + tb * I.ldD;
+                pidx2 = I.offC + tb;
+            }
         } else {
             n = I.N - 1;
             blk = C + I.offC + b * (long long)(I.N - 1) * (I.N - 1);
@@ -102,18 +71,27 @@ __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __res
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
     for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
     wave_sync();
-    const double S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr);
+    const double S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, twin, nullptr, nullptr);
     if (active && lane == 0) {
         T* parent = (FAM == kFamD) ? C : B;
-        if constexpr (sizeof(T) == 8)
+        if constexpr (sizeof(T) == 8) {
             parent[pidx] = parent[pidx] + S;
-        else
+            if (pidx2 >= 0) parent[pidx2] = parent[pidx2] + S;
+        } else {
             parent[pidx] = to_float_down(add_down((double)parent[pidx], S));
-        if (values) values[pidx] = S;
+            if (pidx2 >= 0) parent[pidx2] = to_float_down(add_down((double)parent[pidx2], S));
+        }
+        if (values) {
+            values[pidx] = S;
+            if (pidx2 >= 0) values[pidx2] = S;
+        }
     }
 }
 
-// B -> LB' with K columns per lane (see k_lap_B).
+// B -> LB' and LB += LB' (steps 7-8), one problem of size N per instance of
+// the class, K columns per lane.  lb[2k] = LB, lb[2k+1] = LB' (FP64; in FP32
+// certified mode the bound accumulates rounding toward -inf).  The instance's
+// trace gets (LB, LB') at position counter[k]++ when below trace_cap.
 template <typename T, int SEG, int K>
 __global__ __launch_bounds__(64) void k_lap_B_s(T* __restrict__ B, const Inst* __restrict__ inst, FamilyClass fc,
                                                 int nmax, double* __restrict__ lb, double* __restrict__ trace,
@@ -133,47 +111,7 @@ __global__ __launch_bounds__(64) void k_lap_B_s(T* __restrict__ B, const Inst* _
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
     for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
     wave_sync();
-    const double S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr);
-    if (active && lane == 0) {
-        const double L = (sizeof(T) == 4) ? add_down(lb[2 * k], S) : lb[2 * k] + S;
-        lb[2 * k] = L;
-        lb[2 * k + 1] = S;
-        if (values) values[k] = S;
-        if (counter) {
-            const long long t = counter[k];
-            if (t < trace_cap) {
-                trace[(k * trace_cap + t) * 2] = L;
-                trace[(k * trace_cap + t) * 2 + 1] = S;
-            }
-            counter[k] = t + 1;
-        }
-    }
-}
-
-// B -> LB' and LB += LB' (steps 7-8), one problem of size N per instance of
-// the class.  lb[2k] = LB, lb[2k+1] = LB' (FP64; in FP32 certified mode the
-// bound accumulates rounding toward -inf).  The instance's trace gets
-// (LB, LB') at position counter[k]++ when below trace_cap.
-template <typename T, int SEG>
-__global__ __launch_bounds__(64) void k_lap_B(T* __restrict__ B, const Inst* __restrict__ inst, FamilyClass fc,
-                                              int nmax, double* __restrict__ lb, double* __restrict__ trace,
-                                              long long* __restrict__ counter, long long trace_cap,
-                                              double* __restrict__ values)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int LPW = 64 / SEG;
-    const int seg = threadIdx.x / SEG;
-    const int lane = threadIdx.x & (SEG - 1);
-    const long long x = (long long)blockIdx.x * LPW + seg;
-    const bool active = x < fc.total;
-    const int k = active ? fc.cls[x] : 0;
-    const Inst I = inst[k];
-    const int n = active ? I.N : 0;
-    T* blk = B + I.offB;
-    const SegScratch<T, SEG> sc(smem + seg * SegLds<T, SEG>::bytes(nmax), n);
-    for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
-    wave_sync();
-    const double S = lap_concentrate_seg<T, SEG>(sc, n, active ? blk : nullptr, nullptr, nullptr);
+    const double S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr, nullptr);
     if (active && lane == 0) {
         const double L = (sizeof(T) == 4) ? add_down(lb[2 * k], S) : lb[2 * k] + S;
         lb[2 * k] = L;

@@ -76,6 +76,7 @@ struct qap_rlt2 {
     int trace_level = 1;
     int use_graph = 1;
     int autotune = 1;
+    int dmode = qap::kHalfTwin;   // enumeration of the D family (kAllBlocks or kHalfTwin)
     bool tuned = false;
     size_t lds_limit = 65536;   // dynamic LDS a workgroup may request
     std::string tune_cache;
@@ -141,7 +142,8 @@ size_t slot_lds_any(int seg, int k, int nmax)
 }
 
 template <typename T, int SEG, int K>
-hipError_t launch_family_sk(qap_rlt2* h, int famk, const ClassHost& c, qap::FamilyClass fc, double* values)
+hipError_t launch_family_sk(qap_rlt2* h, int famk, const ClassHost& c, qap::FamilyClass fc, double* values,
+                            int mode)
 {
     if (fc.total <= 0) return hipSuccess;
     constexpr int LPW = 64 / SEG;
@@ -153,19 +155,19 @@ hipError_t launch_family_sk(qap_rlt2* h, int famk, const ClassHost& c, qap::Fami
     T* B = static_cast<T*>(h->dB);
     if (famk == qap::kFamD)
         hipLaunchKernelGGL((qap::k_lap_family_s<T, SEG, K, qap::kFamD>), dim3(grid), dim3(64), lds, h->stream, D, C,
-                           B, h->dInst, fc, c.nmax, values);
+                           B, h->dInst, fc, c.nmax, values, mode);
     else
         hipLaunchKernelGGL((qap::k_lap_family_s<T, SEG, K, qap::kFamC>), dim3(grid), dim3(64), lds, h->stream, D, C,
-                           B, h->dInst, fc, c.nmax, values);
+                           B, h->dInst, fc, c.nmax, values, qap::kAllBlocks);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_family_class(qap_rlt2* h, int famk, const ClassHost& c, qap::FamilyClass fc, int seg, int k,
-                               double* values)
+                               double* values, int mode)
 {
 #define QAP_CFG(SG, KK) \
-    if (seg == SG && k == KK) return launch_family_sk<T, SG, KK>(h, famk, c, fc, values);
+    if (seg == SG && k == KK) return launch_family_sk<T, SG, KK>(h, famk, c, fc, values, mode);
     QAP_CFG(8, 1) QAP_CFG(8, 2) QAP_CFG(8, 3) QAP_CFG(8, 4) QAP_CFG(8, 5) QAP_CFG(8, 6) QAP_CFG(8, 8)
     QAP_CFG(16, 1) QAP_CFG(16, 2) QAP_CFG(16, 3) QAP_CFG(16, 4) QAP_CFG(32, 1) QAP_CFG(32, 2) QAP_CFG(64, 1)
 #undef QAP_CFG
@@ -177,7 +179,7 @@ hipError_t launch_family(qap_rlt2* h, int famk, double* values)
 {
     for (const ClassHost& c : h->fam[famk]) {
         if (c.total <= 0) continue;
-        hipError_t e = launch_family_class<T>(h, famk, c, c.dev(), c.seg_run, c.k_run, values);
+        hipError_t e = launch_family_class<T>(h, famk, c, c.dev(), c.seg_run, c.k_run, values, h->dmode);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -266,11 +268,18 @@ hipError_t tune_family(qap_rlt2* h, int famk)
         while (kk + 1 < (int)c.pre.size() && c.pre[kk + 1] <= X - 1) ++kk;
         const qap::Inst& I0 = h->inst[c.ids[0]];
         const qap::Inst& IL = h->inst[c.ids[kk]];
-        const long long bl = X - 1 - c.pre[kk];
+        long long bl = X - 1 - c.pre[kk];
         long long blk0, blk1, par0, par1;
         char* blkbase;
         char* parbase;
+        // Half-block runs do not write the complements, and the blocks of the
+        // first X half indices lie at or below that of the last one.
+        const int mode = h->dmode == qap::kAllBlocks ? qap::kAllBlocks : qap::kHalfNoTwin;
         if (famk == qap::kFamD) {
+            if (mode != qap::kAllBlocks) {
+                long long twin = 0;
+                qap::half_block(IL.N, bl, &bl, &twin);
+            }
             blk0 = I0.offD;
             blk1 = IL.offD + (bl + 1) * IL.ldD;
             par0 = I0.offC;
@@ -321,7 +330,7 @@ hipError_t tune_family(qap_rlt2* h, int famk)
                 if ((e = hipMemcpyAsync(b0, sblk, bbytes, hipMemcpyDeviceToDevice, h->stream)) != hipSuccess ||
                     (e = hipMemcpyAsync(p0, spar, pbytes, hipMemcpyDeviceToDevice, h->stream)) != hipSuccess ||
                     (e = hipEventRecord(ev0, h->stream)) != hipSuccess ||
-                    (e = launch_family_class<T>(h, famk, c, fc, seg, k, nullptr)) != hipSuccess ||
+                    (e = launch_family_class<T>(h, famk, c, fc, seg, k, nullptr, mode)) != hipSuccess ||
                     (e = hipEventRecord(ev1, h->stream)) != hipSuccess ||
                     (e = hipEventSynchronize(ev1)) != hipSuccess ||
                     (e = hipEventElapsedTime(&ms, ev0, ev1)) != hipSuccess) {
@@ -569,6 +578,7 @@ qap_status qap_rlt2_default_opts(qap_rlt2_opts* o)
     o->use_graph = 1;
     o->autotune = 1;
     o->tune_cache = nullptr;
+    o->complementary = 1;
     return QAP_OK;
 }
 
@@ -620,6 +630,7 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
     h->use_graph = o.use_graph ? 1 : 0;
     h->autotune = o.autotune ? 1 : 0;
     if (o.tune_cache) h->tune_cache = o.tune_cache;
+    h->dmode = o.complementary ? qap::kHalfTwin : qap::kAllBlocks;
     h->elem = o.precision == QAP_FP64 ? sizeof(double) : sizeof(float);
     h->tLB.resize(count);
     h->tLBp.resize(count);
@@ -695,7 +706,8 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
             c.nmax = std::max(c.nmax, n);
             c.ids.push_back(k);
             c.pre.push_back(c.total);
-            c.total += (f == 0) ? (long long)N * N * (N - 1) * (N - 1) : (f == 1) ? (long long)N * N : 1;
+            const long long nblk = (long long)N * N * (N - 1) * (N - 1);
+            c.total += (f == 0) ? (h->dmode == qap::kAllBlocks ? nblk : nblk / 2) : (f == 1) ? (long long)N * N : 1;
         }
     }
 

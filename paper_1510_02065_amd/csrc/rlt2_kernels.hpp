@@ -99,6 +99,35 @@ __device__ __forceinline__ int64_t beta_of(int N, int a, int la, int b, int lb) 
     const int n1 = N - 1;
     return ((int64_t)(a * N + la) * n1 + drop1(b, a)) * n1 + drop1(lb, la);
 }
+// Complementary blocks (Section 6): D_{(a,la),(b,lb)} and D_{(b,lb),(a,la)}
+// cover the same rows and columns, and entry (c,lc) of each belongs to the
+// same six-way group of equation (11).  After the six-way transfer every
+// member of a group holds the same value, so the two blocks are equal and one
+// assignment solve serves both.  Half index h in [0, N^2 (N-1)^2 / 2) lists
+// the blocks with a < b in block order (a, la, b, lb); *beta gets the block
+// and *twin its complement.  The first N (N-1)^2 half indices are blocks
+// 0 .. N (N-1)^2 - 1 (a = 0), and the blocks of half indices 0..h-1 all lie
+// below *beta.
+__host__ __device__ __forceinline__ void half_block(int N, long long h, long long* beta, long long* twin)
+{
+    const int n1 = N - 1;
+    int a = 0;
+    long long per = (long long)N * n1 * n1;   // half blocks with this a: N (N-1-a) (N-1)
+    while (h >= per) {
+        h -= per;
+        ++a;
+        per -= (long long)N * n1;
+    }
+    const long long w = (long long)(n1 - a) * n1;   // blocks of super-block (a, la) with b > a
+    const int la = (int)(h / w);
+    const long long r = h - (long long)la * w;
+    const int bq = a + (int)(r / n1);                // compact b (b > a, so b = bq + 1)
+    const int lq = (int)(r % n1);
+    const int b = bq + 1, lb = lq + (lq >= la);
+    *beta = ((long long)(a * N + la) * n1 + bq) * n1 + lq;
+    *twin = ((long long)(b * N + lb) * n1 + a) * n1 + (la - (la > lb));
+}
+
 // Offset of d_{(a,la),(b,lb),(c,lc)} inside block beta_of(a,la,b,lb).
 __device__ __forceinline__ int entry_of(int N, int a, int la, int b, int lb, int c, int lc) {
     return drop2(c, a, b) * (N - 2) + drop2(lc, la, lb);
