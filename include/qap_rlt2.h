@@ -20,7 +20,9 @@
  *  - Handles are not thread-safe: use one handle from one thread at a time.
  *  - Sizes: 3 <= N <= QAP_RLT2_MAX_N.  The reduced-cost array D has
  *    N^2 (N-1)^2 (N-2)^2 entries (8 bytes each in FP64 mode, 4 in FP32 mode);
- *    creation fails with QAP_ENOMEM if it does not fit in free device memory.
+ *    the device holds one block of each complementary pair, half of them,
+ *    unless the option `complementary` is 0.  Creation fails with
+ *    QAP_ENOMEM if it does not fit in free device memory.
  *
  * Compact layouts used by qap_rlt2_read_state and qap_rlt2_lap_values
  * --------------------------------------------------------------------
@@ -79,11 +81,13 @@ typedef struct {
                          fits in LDS                                          */
     const char* tune_cache; /* nullable path of a text file that stores the
                          tuned choices and is read back by later handles     */
-    int complementary; /* 1 (default): concentrate each pair of complementary
-                         D blocks D_ijkn, D_knij (Section 6) once and write the
-                         residual and S to both: after the six-way transfer of
-                         step 3 the two blocks are equal, so the state is bit
-                         for bit that of 0, which concentrates every block    */
+    int complementary; /* 1 (default): store one block of each pair of
+                         complementary D blocks D_ijkn, D_knij (Section 6) and
+                         concentrate it once, S going to both c_ijkn and
+                         c_knij.  The six-way transfer leaves the two blocks
+                         equal and a concentration keeps them so, so the state
+                         is bit for bit that of 0, which stores and
+                         concentrates every block, with half the memory     */
 } qap_rlt2_opts;
 
 typedef struct qap_rlt2 qap_rlt2;
@@ -160,7 +164,9 @@ qap_status qap_rlt2_trace(qap_rlt2* h, int64_t capacity, int64_t* count,
 qap_status qap_rlt2_lap_values(qap_rlt2* h, double* sD, double* sC, double* sB);
 
 /* Copy the current dual state to host FP64 arrays in the compact layouts
- * above (FP32 state is widened exactly).  Each pointer may be NULL. */
+ * above (FP32 state is widened exactly; with one stored block per
+ * complementary pair, both blocks of the pair receive it).  Each pointer may
+ * be NULL. */
 qap_status qap_rlt2_read_state(qap_rlt2* h, double* lb, double* B, double* C, double* D);
 
 /* Release the handle and all of its device memory.  NULL-safe. */

@@ -21,11 +21,12 @@ struct FamilyClass {
 
 enum : int { kFamD = 0, kFamC = 1 };
 
-// How the D family is enumerated (see half_block).
+// How the D family is stored and enumerated (see half_block).
 enum : int {
-    kAllBlocks = 0,    // problem b is block b
-    kHalfNoTwin = 1,   // problem b is half block b; the complement is not written
-    kHalfTwin = 2,     // problem b is half block b; residual and S also go to the complement
+    kAllBlocks = 0,    // every block stored; problem b is block b, parent c_b
+    kHalfStore = 1,    // one block per complementary pair stored; problem h is
+                       // stored block h, parents c_beta and c_twin
+    kHalfStoreTune = 2 // as kHalfStore, parent c_beta only (tuning runs)
 };
 
 // D -> C (FAM kFamD: blocks D_beta of size N-2, parent c_beta) or C -> B
@@ -46,7 +47,6 @@ __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __res
     const bool active = x < fc.total;
     int n = 0;
     T* blk = nullptr;
-    T* twin = nullptr;
     long long pidx = 0, pidx2 = -1;
     if (active) {
         const int kk = find_seg(fc.pre, fc.Kc, x);
@@ -54,14 +54,11 @@ __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __res
         const long long b = x - fc.pre[kk];
         if (FAM == kFamD) {
             n = I.N - 2;
+            blk = D + I.offD + b * I.ldD;
             long long beta = b, tb = -1;
             if (mode != kAllBlocks) half_block(I.N, b, &beta, &tb);
-            blk = D + I.offD + beta * I.ldD;
             pidx = I.offC + beta;
-            if (mode == kHalfTwin) {
-                twin = D + I.offD + tb * I.ldD;
-                pidx2 = I.offC + tb;
-            }
+            if (mode == kHalfStore) pidx2 = I.offC + tb;
         } else {
             n = I.N - 1;
             blk = C + I.offC + b * (long long)(I.N - 1) * (I.N - 1);
@@ -71,7 +68,7 @@ __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __res
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
     for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
     wave_sync();
-    const double S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, twin, nullptr, nullptr);
+    const double S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr);
     if (active && lane == 0) {
         T* parent = (FAM == kFamD) ? C : B;
         if constexpr (sizeof(T) == 8) {
@@ -111,7 +108,7 @@ __global__ __launch_bounds__(64) void k_lap_B_s(T* __restrict__ B, const Inst* _
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
     for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
     wave_sync();
-    const double S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr, nullptr);
+    const double S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr);
     if (active && lane == 0) {
         const double L = (sizeof(T) == 4) ? add_down(lb[2 * k], S) : lb[2 * k] + S;
         lb[2 * k] = L;

@@ -159,15 +159,14 @@ struct SlotScratch {
 };
 
 // Solve, canonicalise and write residuals for the n x n matrix sc.M (in LDS,
-// row stride n, left unchanged).  R (nullable) receives the residual, R2
-// (nullable) a second copy of it, duals (nullable) [uc | vc | ur | vr],
-// assign (nullable) the solver's assignment.
+// row stride n, left unchanged).  R (nullable) receives the residual, duals
+// (nullable) [uc | vc | ur | vr], assign (nullable) the solver's assignment.
 // Returns S to every lane of the segment.  Called by whole waves; segments may
 // have different n (0 <= n <= SEG*K).
 template <typename T, int SEG, int K>
 __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG, K>& sc, int n,
-                                                        T* __restrict__ R, T* __restrict__ R2,
-                                                        T* __restrict__ duals, int32_t* __restrict__ assign)
+                                                        T* __restrict__ R, T* __restrict__ duals,
+                                                        int32_t* __restrict__ assign)
 {
     using S = SegS<SEG>;
     constexpr int NONE = 1 << 20;   // larger than any column index
@@ -419,9 +418,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
                     const T m = M[r * n + c[s]];
                     const T r1 = (m - vc[s]) - (T)sc.va[r];
                     const T r2 = (m - (T)sc.vb[r]) - vr[s];
-                    const T v = (T)0.5 * (r1 + r2);
-                    R[r * n + c[s]] = v;
-                    if (R2 != nullptr) R2[r * n + c[s]] = v;
+                    R[r * n + c[s]] = (T)0.5 * (r1 + r2);
                 }
             }
         }
@@ -476,11 +473,8 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
         if (R != nullptr) {
             for (int s = 0; s < K; ++s) {
                 if (!ok[s]) continue;
-                for (int r = 0; r < n; ++r) {
-                    const T v = to_float_down(sub_down(sub_down((double)M[r * n + c[s]], V[s]), sc.va[r]));
-                    R[r * n + c[s]] = v;
-                    if (R2 != nullptr) R2[r * n + c[s]] = v;
-                }
+                for (int r = 0; r < n; ++r)
+                    R[r * n + c[s]] = to_float_down(sub_down(sub_down((double)M[r * n + c[s]], V[s]), sc.va[r]));
             }
         }
         double su = 0.0, sv = 0.0;

@@ -76,7 +76,7 @@ struct qap_rlt2 {
     int trace_level = 1;
     int use_graph = 1;
     int autotune = 1;
-    int dmode = qap::kHalfTwin;   // enumeration of the D family (kAllBlocks or kHalfTwin)
+    int dmode = qap::kHalfStore;   // D storage and enumeration (kAllBlocks or kHalfStore)
     bool tuned = false;
     size_t lds_limit = 65536;   // dynamic LDS a workgroup may request
     std::string tune_cache;
@@ -268,22 +268,20 @@ hipError_t tune_family(qap_rlt2* h, int famk)
         while (kk + 1 < (int)c.pre.size() && c.pre[kk + 1] <= X - 1) ++kk;
         const qap::Inst& I0 = h->inst[c.ids[0]];
         const qap::Inst& IL = h->inst[c.ids[kk]];
-        long long bl = X - 1 - c.pre[kk];
+        const long long bl = X - 1 - c.pre[kk];
         long long blk0, blk1, par0, par1;
         char* blkbase;
         char* parbase;
-        // Half-block runs do not write the complements, and the blocks of the
-        // first X half indices lie at or below that of the last one.
-        const int mode = h->dmode == qap::kAllBlocks ? qap::kAllBlocks : qap::kHalfNoTwin;
+        // Tuning runs on stored half blocks write only the parent c_beta, and
+        // the parents of the first X half blocks lie at or below the last one's.
+        const int mode = h->dmode == qap::kAllBlocks ? qap::kAllBlocks : qap::kHalfStoreTune;
         if (famk == qap::kFamD) {
-            if (mode != qap::kAllBlocks) {
-                long long twin = 0;
-                qap::half_block(IL.N, bl, &bl, &twin);
-            }
+            long long pl = bl, twin = 0;
+            if (mode != qap::kAllBlocks) qap::half_block(IL.N, bl, &pl, &twin);
             blk0 = I0.offD;
             blk1 = IL.offD + (bl + 1) * IL.ldD;
             par0 = I0.offC;
-            par1 = IL.offC + bl + 1;
+            par1 = IL.offC + pl + 1;
             blkbase = static_cast<char*>(h->dD);
             parbase = static_cast<char*>(h->dC);
         } else {
@@ -445,8 +443,12 @@ hipError_t enqueue_step(qap_rlt2* h, int step)
                            h->dInst, h->dPreC, h->K, h->totalC);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((qap::k_sweep<T>), dim3((unsigned)h->totalWG), dim3(256), 0, st, D, CC, B, h->dTri,
-                           h->dInst, h->dPreWG, h->K, h->totalB);
+        if (h->dmode == qap::kAllBlocks)
+            hipLaunchKernelGGL((qap::k_sweep<T, false>), dim3((unsigned)h->totalWG), dim3(256), 0, st, D, CC, B,
+                               h->dTri, h->dInst, h->dPreWG, h->K, h->totalB);
+        else
+            hipLaunchKernelGGL((qap::k_sweep<T, true>), dim3((unsigned)h->totalWG), dim3(256), 0, st, D, CC, B,
+                               h->dTri, h->dInst, h->dPreWG, h->K, h->totalB);
         return hipGetLastError();
     }
     case 4:
@@ -468,9 +470,14 @@ template <typename T>
 hipError_t enqueue_certify(qap_rlt2* h)
 {
     hipStream_t st = h->stream;
-    hipLaunchKernelGGL((qap::k_cert_D<T>), dim3(grid_for(h->totalC, 4)), dim3(256), 0, st,
-                       static_cast<const T*>(h->dD), static_cast<const T*>(h->dC), h->dCt, h->dInst, h->dPreC,
-                       h->K, h->totalC);
+    if (h->dmode == qap::kAllBlocks)
+        hipLaunchKernelGGL((qap::k_cert_D<T, false>), dim3(grid_for(h->totalC, 4)), dim3(256), 0, st,
+                           static_cast<const T*>(h->dD), static_cast<const T*>(h->dC), h->dCt, h->dInst, h->dPreC,
+                           h->K, h->totalC);
+    else
+        hipLaunchKernelGGL((qap::k_cert_D<T, true>), dim3(grid_for(h->totalC / 2, 4)), dim3(256), 0, st,
+                           static_cast<const T*>(h->dD), static_cast<const T*>(h->dC), h->dCt, h->dInst, h->dPreC,
+                           h->K, h->totalC);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((qap::k_cert_C<T>), dim3(grid_for(h->totalB, 4)), dim3(256), 0, st, h->dCt,
@@ -630,7 +637,7 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
     h->use_graph = o.use_graph ? 1 : 0;
     h->autotune = o.autotune ? 1 : 0;
     if (o.tune_cache) h->tune_cache = o.tune_cache;
-    h->dmode = o.complementary ? qap::kHalfTwin : qap::kAllBlocks;
+    h->dmode = o.complementary ? qap::kHalfStore : qap::kAllBlocks;
     h->elem = o.precision == QAP_FP64 ? sizeof(double) : sizeof(float);
     h->tLB.resize(count);
     h->tLBp.resize(count);
@@ -691,7 +698,7 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
         const long long nC = (long long)N * N * n1 * n1;
         h->totalB += (long long)N * N;
         h->totalC += nC;
-        h->totalD += nC * I.ldD;
+        h->totalD += (h->dmode == qap::kAllBlocks ? nC : nC / 2) * I.ldD;
         h->totalWG += 8LL * ((I.ntri + 7) / 8) * I.wpt;
     }
     // Segment-size classes of the three families.
@@ -1029,7 +1036,22 @@ qap_status qap_rlt2_instance_state(qap_rlt2* h, int k, double* lb, double* B, do
     const char* d = static_cast<const char*>(h->dD) + I.offD * h->elem;
     if (B) QAP_HIP(widen(B, b, (long long)N * N, (size_t)N * N * h->elem, 1));
     if (C) QAP_HIP(widen(C, c, nC, (size_t)nC * h->elem, 1));
-    if (D) QAP_HIP(widen(D, d, blk, I.ldD * h->elem, nC));
+    if (D) {
+        if (h->dmode == qap::kAllBlocks) {
+            QAP_HIP(widen(D, d, blk, I.ldD * h->elem, nC));
+        } else {
+            // One stored block per complementary pair: copy both ways.
+            std::vector<double> half((size_t)(nC / 2) * blk);
+            QAP_HIP(widen(half.data(), d, blk, I.ldD * h->elem, nC / 2));
+            double* out = D;
+            for (long long hb = 0; hb < nC / 2; ++hb) {
+                long long beta = 0, twin = 0;
+                qap::half_block(N, hb, &beta, &twin);
+                std::copy(half.begin() + hb * blk, half.begin() + (hb + 1) * blk, out + beta * blk);
+                std::copy(half.begin() + hb * blk, half.begin() + (hb + 1) * blk, out + twin * blk);
+            }
+        }
+    }
     return QAP_OK;
 }
 

@@ -101,13 +101,15 @@ __device__ __forceinline__ int64_t beta_of(int N, int a, int la, int b, int lb) 
 }
 // Complementary blocks (Section 6): D_{(a,la),(b,lb)} and D_{(b,lb),(a,la)}
 // cover the same rows and columns, and entry (c,lc) of each belongs to the
-// same six-way group of equation (11).  After the six-way transfer every
-// member of a group holds the same value, so the two blocks are equal and one
-// assignment solve serves both.  Half index h in [0, N^2 (N-1)^2 / 2) lists
-// the blocks with a < b in block order (a, la, b, lb); *beta gets the block
-// and *twin its complement.  The first N (N-1)^2 half indices are blocks
-// 0 .. N (N-1)^2 - 1 (a = 0), and the blocks of half indices 0..h-1 all lie
-// below *beta.
+// same six-way group of equation (11).  The six-way transfer leaves every
+// member of a group with the same value and a concentration leaves both blocks
+// with the same residual, so from D = 0 on the two blocks are always equal:
+// the handle stores one copy, the block with a < b.  Half index h in
+// [0, N^2 (N-1)^2 / 2) lists those blocks in block order (a, la, b, lb).
+//
+// half_block: *beta gets the block number (position of its c in C) of half
+// index h and *twin that of its complement.  beta grows with h, so the blocks
+// of half indices 0..h all lie at or below *beta.
 __host__ __device__ __forceinline__ void half_block(int N, long long h, long long* beta, long long* twin)
 {
     const int n1 = N - 1;
@@ -126,6 +128,25 @@ __host__ __device__ __forceinline__ void half_block(int N, long long h, long lon
     const int b = bq + 1, lb = lq + (lq >= la);
     *beta = ((long long)(a * N + la) * n1 + bq) * n1 + lq;
     *twin = ((long long)(b * N + lb) * n1 + a) * n1 + (la - (la > lb));
+}
+
+// Half index of D_{(a,la),(b,lb)} for a < b (the inverse of half_block).
+__host__ __device__ __forceinline__ long long half_index(int N, int a, int la, int b, int lb)
+{
+    const long long n1 = N - 1;
+    const long long before = (long long)N * n1 * ((long long)a * n1 - (long long)a * (a - 1) / 2);
+    return before + (long long)la * (n1 - a) * n1 + (long long)(b - 1 - a) * n1 + (lb - (lb > la));
+}
+
+// Half index of the stored copy of block beta (either member of its pair).
+__host__ __device__ __forceinline__ long long half_of_beta(int N, long long beta)
+{
+    const long long n1 = N - 1;
+    const int ln = (int)(beta % n1), kq = (int)((beta / n1) % n1);
+    const int ij = (int)(beta / (n1 * n1));
+    const int a = ij / N, la = ij % N;
+    const int b = kq + (kq >= a), lb = ln + (ln >= la);
+    return a < b ? half_index(N, a, la, b, lb) : half_index(N, b, lb, a, la);
 }
 
 // Offset of d_{(a,la),(b,lb),(c,lc)} inside block beta_of(a,la,b,lb).
@@ -241,7 +262,14 @@ __global__ __launch_bounds__(256) void k_spread_prep(T* __restrict__ C, const T*
 // triple's six sub-arrays (6 N(N-1)(N-2) entries) together and the partially
 // used cache lines of the four strided members meet in its L2.
 // The first totalB threads of the grid also clear B.
-template <typename T>
+//
+// HALF: only the block with the smaller facility of each complementary pair
+// is stored (half_index).  As i < k < p, members (P1 P2 P3) and (P2 P1 P3)
+// share the stored entry A, (P1 P3 P2) and (P3 P1 P2) share B, and
+// (P2 P3 P1) and (P3 P2 P1) share C; each member still gets its own block's
+// spread share, in the same order, so the sum has the same bits as with
+// every block stored.
+template <typename T, bool HALF>
 __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __restrict__ CC,
                                                T* __restrict__ B, const int* __restrict__ tri,
                                                const Inst* __restrict__ inst,
@@ -274,12 +302,22 @@ __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __re
     const int64_t b0 = beta_of(N, i, j, k, n), b1 = beta_of(N, i, j, p, q);
     const int64_t b2 = beta_of(N, k, n, i, j), b3 = beta_of(N, k, n, p, q);
     const int64_t b4 = beta_of(N, p, q, i, j), b5 = beta_of(N, p, q, k, n);
-    const int64_t a0 = b0 * ldD + entry_of(N, i, j, k, n, p, q);
-    const int64_t a1 = b1 * ldD + entry_of(N, i, j, p, q, k, n);
-    const int64_t a2 = b2 * ldD + entry_of(N, k, n, i, j, p, q);
-    const int64_t a3 = b3 * ldD + entry_of(N, k, n, p, q, i, j);
-    const int64_t a4 = b4 * ldD + entry_of(N, p, q, i, j, k, n);
-    const int64_t a5 = b5 * ldD + entry_of(N, p, q, k, n, i, j);
+    int64_t a0, a1, a2, a3, a4, a5;
+    if constexpr (HALF) {
+        a0 = half_index(N, i, j, k, n) * ldD + entry_of(N, i, j, k, n, p, q);
+        a1 = half_index(N, i, j, p, q) * ldD + entry_of(N, i, j, p, q, k, n);
+        a3 = half_index(N, k, n, p, q) * ldD + entry_of(N, k, n, p, q, i, j);
+        a2 = a0;
+        a4 = a1;
+        a5 = a3;
+    } else {
+        a0 = b0 * ldD + entry_of(N, i, j, k, n, p, q);
+        a1 = b1 * ldD + entry_of(N, i, j, p, q, k, n);
+        a2 = b2 * ldD + entry_of(N, k, n, i, j, p, q);
+        a3 = b3 * ldD + entry_of(N, k, n, p, q, i, j);
+        a4 = b4 * ldD + entry_of(N, p, q, i, j, k, n);
+        a5 = b5 * ldD + entry_of(N, p, q, k, n, i, j);
+    }
 
     T mean;
     if constexpr (sizeof(T) == 8) {
@@ -312,10 +350,12 @@ __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __re
     }
     Dk[a0] = mean;
     Dk[a1] = mean;
-    Dk[a2] = mean;
     Dk[a3] = mean;
-    Dk[a4] = mean;
-    Dk[a5] = mean;
+    if constexpr (!HALF) {
+        Dk[a2] = mean;
+        Dk[a4] = mean;
+        Dk[a5] = mean;
+    }
 }
 
 // Step 5: the complementary pair c_ijkn, c_knij (equation (10)) both become
@@ -352,22 +392,37 @@ __global__ __launch_bounds__(256) void k_transfer_C(T* __restrict__ C, const Ins
 // b~ = b + (N-1) min(0, min of C~_ij), and LB + N min(0, min b~) bounds the
 // whole sum from below whatever the signs of the stored entries.
 
-// One wave per D block of every instance: ct[beta] = c_beta + (N-2) min(0, min D_beta).
-template <typename T>
+// One wave per stored D block of every instance: ct[beta] = c_beta +
+// (N-2) min(0, min D_beta), for both blocks of the pair when HALF.  The
+// blocks stored (all, or one per pair) number totalC (or totalC / 2; every
+// instance's C count is a multiple of 4, so halving preC gives the prefix of
+// its stored blocks).
+template <typename T, bool HALF>
 __global__ __launch_bounds__(256) void k_cert_D(const T* __restrict__ Dd, const T* __restrict__ C,
                                                 double* __restrict__ ct, const Inst* __restrict__ inst,
                                                 const long long* __restrict__ preC, int K, long long totalC)
 {
     const long long x = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (x >= totalC) return;
-    const Inst I = inst[find_seg(preC, K, x)];
+    if (x >= (HALF ? totalC / 2 : totalC)) return;
+    const Inst I = inst[find_seg(preC, K, HALF ? 2 * x : x)];
     const int N = I.N, blk = (N - 2) * (N - 2);
-    const T* __restrict__ Db = Dd + I.offD + (x - I.offC) * I.ldD;
+    const long long local = x - (HALF ? I.offC / 2 : I.offC);
+    const T* __restrict__ Db = Dd + I.offD + local * I.ldD;
     double m = 0.0;
     for (int e = lane; e < blk; e += 64) m = __builtin_fmin(m, (double)Db[e]);
     for (int off = 32; off > 0; off >>= 1) m = __builtin_fmin(m, __shfl_xor(m, off, 64));
-    if (lane == 0) ct[x] = add_down((double)C[x], mul_down((double)(N - 2), m));
+    if (lane == 0) {
+        const double md = mul_down((double)(N - 2), m);
+        if constexpr (HALF) {
+            long long beta, twin;
+            half_block(N, local, &beta, &twin);
+            ct[I.offC + beta] = add_down((double)C[I.offC + beta], md);
+            ct[I.offC + twin] = add_down((double)C[I.offC + twin], md);
+        } else {
+            ct[x] = add_down((double)C[x], md);
+        }
+    }
 }
 
 // One wave per C block of every instance: bt[ij] = b_ij + (N-1) min(0, min C~_ij).
