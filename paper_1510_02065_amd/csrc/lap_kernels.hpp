@@ -68,7 +68,11 @@ __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __res
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
     for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
     wave_sync();
-    const double S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr);
+    double S;
+    if constexpr (K == 1)
+        S = lap_concentrate_flat<T, SEG>(sc, n, active ? blk : nullptr, nullptr, nullptr);
+    else
+        S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr);
     if (active && lane == 0) {
         T* parent = (FAM == kFamD) ? C : B;
         if constexpr (sizeof(T) == 8) {
@@ -108,7 +112,11 @@ __global__ __launch_bounds__(64) void k_lap_B_s(T* __restrict__ B, const Inst* _
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
     for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
     wave_sync();
-    const double S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr);
+    double S;
+    if constexpr (K == 1)
+        S = lap_concentrate_flat<T, SEG>(sc, n, active ? blk : nullptr, nullptr, nullptr);
+    else
+        S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr);
     if (active && lane == 0) {
         const double L = (sizeof(T) == 4) ? add_down(lb[2 * k], S) : lb[2 * k] + S;
         lb[2 * k] = L;

@@ -158,151 +158,26 @@ struct SlotScratch {
     }
 };
 
-// Solve, canonicalise and write residuals for the n x n matrix sc.M (in LDS,
-// row stride n, left unchanged).  R (nullable) receives the residual, duals
-// (nullable) [uc | vc | ur | vr], assign (nullable) the solver's assignment.
-// Returns S to every lane of the segment.  Called by whole waves; segments may
-// have different n (0 <= n <= SEG*K).
+// Canonical dual and residual, from the solver's optimal duals and matching:
+// v (column duals) and p (row matched to each column) of this lane's K
+// columns, ucol the dual of that row; the LDS copies sc.p (row indices) and
+// sc.u (row dual per column) hold the same for every column.
 template <typename T, int SEG, int K>
-__device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG, K>& sc, int n,
-                                                        T* __restrict__ R, T* __restrict__ duals,
-                                                        int32_t* __restrict__ assign)
+__device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG, K>& sc, int n,
+                                                       T* __restrict__ R, T* __restrict__ duals,
+                                                       int32_t* __restrict__ assign, const T (&v)[K],
+                                                       const int (&p)[K], const T (&ucol)[K])
 {
     using S = SegS<SEG>;
     constexpr int NONE = 1 << 20;   // larger than any column index
     const T* __restrict__ M = sc.M;
     const int lane = S::lane();
     const T INF = inf_of<T>();
-
-    int c[K];      // this lane's columns (also its rows in the row passes)
+    int c[K];
     bool ok[K];
     for (int s = 0; s < K; ++s) {
         c[s] = s * SEG + lane;
         ok[s] = c[s] < n;
-    }
-
-    // ---- column reduction ---------------------------------------------------
-    T v[K];        // column duals
-    int p[K];      // row matched to each column (or -1)
-    T ucol[K];     // dual of that row
-    int crow[K];
-    for (int s = 0; s < K; ++s) {
-        v[s] = 0;
-        crow[s] = 0;
-        if (ok[s]) {
-            v[s] = M[c[s]];
-            for (int r = 1; r < n; ++r) {
-                const T m = M[r * n + c[s]];
-                if (m < v[s]) {
-                    v[s] = m;
-                    crow[s] = r;
-                }
-            }
-        }
-        sc.aux[c[s]] = NONE;
-    }
-    wave_sync();
-    for (int s = 0; s < K; ++s)
-        if (ok[s]) atomicMin(&sc.aux[crow[s]], c[s]);
-    wave_sync();
-    for (int s = 0; s < K; ++s) {
-        p[s] = (ok[s] && sc.aux[crow[s]] == c[s]) ? crow[s] : -1;
-        ucol[s] = 0;
-        sc.p[c[s]] = p[s];
-        sc.u[c[s]] = 0.0;
-    }
-    wave_sync();
-
-    // ---- Hungarian method for the rows left free -----------------------------
-    for (int i = 0; i < n; ++i) {
-        if (sc.aux[i] != NONE) continue;   // row i already matched
-        T dist[K];
-        int way[K];
-        bool used[K];
-        for (int s = 0; s < K; ++s) {
-            dist[s] = INF;
-            way[s] = -1;
-            used[s] = false;
-        }
-        int i0 = i;     // row being scanned
-        T ui0 = 0;      // its dual (a free row has dual 0)
-        T d0 = 0;       // distance at which row i0 was reached
-        int j0 = -1;    // column through which row i0 was reached
-        int jend = -1;
-        T dend = 0;
-        for (int pass = 0; pass <= n; ++pass) {
-            T lm = INF;
-            int lc = NONE;
-            for (int s = 0; s < K; ++s) {
-                const bool live = ok[s] && !used[s];
-                const T cur = d0 + ((M[i0 * n + (ok[s] ? c[s] : 0)] - ui0) - v[s]);
-                if (live && cur < dist[s]) {
-                    dist[s] = cur;
-                    way[s] = j0;
-                }
-                if (live && dist[s] < lm) {
-                    lm = dist[s];
-                    lc = c[s];
-                }
-            }
-            const T dmin = S::min(lm);
-            const int j1 = S::imin(lm == dmin ? lc : NONE);
-            const int j1c = j1 < n ? j1 : 0;
-            const int pj = j1 < n ? sc.p[j1c] : -1;
-            if (pj < 0) {
-                jend = j1 < n ? j1 : -1;   // no candidate: non-finite costs
-                dend = dmin;
-                break;
-            }
-            for (int s = 0; s < K; ++s) used[s] = used[s] || (c[s] == j1);
-            j0 = j1;
-            i0 = pj;
-            ui0 = (T)sc.u[j1c];
-            d0 = dmin;
-        }
-        // Dual shift of the scanned tree; predecessors published for the flip.
-        for (int s = 0; s < K; ++s) {
-            if (ok[s] && used[s]) {
-                const T sh = dend - dist[s];
-                v[s] -= sh;
-                ucol[s] += sh;
-            }
-            sc.way[c[s]] = way[s];
-            sc.u[c[s]] = (double)ucol[s];
-        }
-        wave_sync();
-        // Flip the path: every column on it takes the row (and row dual) of
-        // its predecessor column; the first one takes the new row.  Columns on
-        // the path are found by walking the predecessors from the end; every
-        // lane walks (the same) path and updates the columns it holds, reading
-        // the old rows and duals from LDS.
-        int newp[K];
-        T newu[K];
-        for (int s = 0; s < K; ++s) {
-            newp[s] = p[s];
-            newu[s] = ucol[s];
-        }
-        for (int j = jend, hop = 0; j >= 0 && j < n && hop <= n; ++hop) {
-            const int w = sc.way[j];
-            const int wc = w >= 0 ? w : 0;
-            const int pw = sc.p[wc];
-            const T uw = (T)sc.u[wc];
-            for (int s = 0; s < K; ++s) {
-                if (c[s] == j) {
-                    newp[s] = w >= 0 ? pw : i;
-                    newu[s] = w >= 0 ? uw : dend;
-                }
-            }
-            j = w;
-        }
-        wave_sync();
-        for (int s = 0; s < K; ++s) {
-            p[s] = newp[s];
-            ucol[s] = newu[s];
-            sc.p[c[s]] = p[s];
-            sc.u[c[s]] = (double)ucol[s];
-        }
-        wave_sync();
     }
 
     // ---- column-canonical point (lanes = columns) ---------------------------
@@ -495,6 +370,311 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
         wave_sync();
         return add_down(su, sv);
     }
+}
+
+// Solve, canonicalise and write residuals for the n x n matrix sc.M (in LDS,
+// row stride n, left unchanged).  R (nullable) receives the residual, duals
+// (nullable) [uc | vc | ur | vr], assign (nullable) the solver's assignment.
+// Returns S to every lane of the segment.  Called by whole waves; segments may
+// have different n (0 <= n <= SEG*K).
+template <typename T, int SEG, int K>
+__device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG, K>& sc, int n,
+                                                        T* __restrict__ R, T* __restrict__ duals,
+                                                        int32_t* __restrict__ assign)
+{
+    using S = SegS<SEG>;
+    constexpr int NONE = 1 << 20;   // larger than any column index
+    const T* __restrict__ M = sc.M;
+    const int lane = S::lane();
+    const T INF = inf_of<T>();
+
+    int c[K];      // this lane's columns (also its rows in the row passes)
+    bool ok[K];
+    for (int s = 0; s < K; ++s) {
+        c[s] = s * SEG + lane;
+        ok[s] = c[s] < n;
+    }
+
+    // ---- column reduction ---------------------------------------------------
+    T v[K];        // column duals
+    int p[K];      // row matched to each column (or -1)
+    T ucol[K];     // dual of that row
+    int crow[K];
+    for (int s = 0; s < K; ++s) {
+        v[s] = 0;
+        crow[s] = 0;
+        if (ok[s]) {
+            v[s] = M[c[s]];
+            for (int r = 1; r < n; ++r) {
+                const T m = M[r * n + c[s]];
+                if (m < v[s]) {
+                    v[s] = m;
+                    crow[s] = r;
+                }
+            }
+        }
+        sc.aux[c[s]] = NONE;
+    }
+    wave_sync();
+    for (int s = 0; s < K; ++s)
+        if (ok[s]) atomicMin(&sc.aux[crow[s]], c[s]);
+    wave_sync();
+    for (int s = 0; s < K; ++s) {
+        p[s] = (ok[s] && sc.aux[crow[s]] == c[s]) ? crow[s] : -1;
+        ucol[s] = 0;
+        sc.p[c[s]] = p[s];
+        sc.u[c[s]] = 0.0;
+    }
+    wave_sync();
+
+    // ---- Hungarian method for the rows left free -----------------------------
+    for (int i = 0; i < n; ++i) {
+        if (sc.aux[i] != NONE) continue;   // row i already matched
+        T dist[K];
+        int way[K];
+        bool used[K];
+        for (int s = 0; s < K; ++s) {
+            dist[s] = INF;
+            way[s] = -1;
+            used[s] = false;
+        }
+        int i0 = i;     // row being scanned
+        T ui0 = 0;      // its dual (a free row has dual 0)
+        T d0 = 0;       // distance at which row i0 was reached
+        int j0 = -1;    // column through which row i0 was reached
+        int jend = -1;
+        T dend = 0;
+        for (int pass = 0; pass <= n; ++pass) {
+            T lm = INF;
+            int lc = NONE;
+            for (int s = 0; s < K; ++s) {
+                const bool live = ok[s] && !used[s];
+                const T cur = d0 + ((M[i0 * n + (ok[s] ? c[s] : 0)] - ui0) - v[s]);
+                if (live && cur < dist[s]) {
+                    dist[s] = cur;
+                    way[s] = j0;
+                }
+                if (live && dist[s] < lm) {
+                    lm = dist[s];
+                    lc = c[s];
+                }
+            }
+            const T dmin = S::min(lm);
+            const int j1 = S::imin(lm == dmin ? lc : NONE);
+            const int j1c = j1 < n ? j1 : 0;
+            const int pj = j1 < n ? sc.p[j1c] : -1;
+            if (pj < 0) {
+                jend = j1 < n ? j1 : -1;   // no candidate: non-finite costs
+                dend = dmin;
+                break;
+            }
+            for (int s = 0; s < K; ++s) used[s] = used[s] || (c[s] == j1);
+            j0 = j1;
+            i0 = pj;
+            ui0 = (T)sc.u[j1c];
+            d0 = dmin;
+        }
+        // Dual shift of the scanned tree; predecessors published for the flip.
+        for (int s = 0; s < K; ++s) {
+            if (ok[s] && used[s]) {
+                const T sh = dend - dist[s];
+                v[s] -= sh;
+                ucol[s] += sh;
+            }
+            sc.way[c[s]] = way[s];
+            sc.u[c[s]] = (double)ucol[s];
+        }
+        wave_sync();
+        // Flip the path: every column on it takes the row (and row dual) of
+        // its predecessor column; the first one takes the new row.  Columns on
+        // the path are found by walking the predecessors from the end; every
+        // lane walks (the same) path and updates the columns it holds, reading
+        // the old rows and duals from LDS.
+        int newp[K];
+        T newu[K];
+        for (int s = 0; s < K; ++s) {
+            newp[s] = p[s];
+            newu[s] = ucol[s];
+        }
+        for (int j = jend, hop = 0; j >= 0 && j < n && hop <= n; ++hop) {
+            const int w = sc.way[j];
+            const int wc = w >= 0 ? w : 0;
+            const int pw = sc.p[wc];
+            const T uw = (T)sc.u[wc];
+            for (int s = 0; s < K; ++s) {
+                if (c[s] == j) {
+                    newp[s] = w >= 0 ? pw : i;
+                    newu[s] = w >= 0 ? uw : dend;
+                }
+            }
+            j = w;
+        }
+        wave_sync();
+        for (int s = 0; s < K; ++s) {
+            p[s] = newp[s];
+            ucol[s] = newu[s];
+            sc.p[c[s]] = p[s];
+            sc.u[c[s]] = (double)ucol[s];
+        }
+        wave_sync();
+    }
+
+    return lap_canonical_finish<T, SEG, K>(sc, n, R, duals, assign, v, p, ucol);
+}
+
+// Lane bits of a predicate over this lane's segment (bit 0 = the segment's
+// first lane), and the lowest set bit (-1 when none).
+template <int SEG>
+struct SegBits {
+    __device__ __forceinline__ static unsigned long long get(bool pred) {
+        const unsigned long long b = __ballot(pred);
+        if constexpr (SEG == 64)
+            return b;
+        else
+            return (b >> (threadIdx.x & (64 - SEG))) & ((1ull << SEG) - 1);
+    }
+    __device__ __forceinline__ static int first(unsigned long long bits) {
+        if constexpr (SEG == 64)
+            return bits ? __builtin_ctzll(bits) : -1;
+        else
+            return bits ? __builtin_ctz((unsigned)bits) : -1;
+    }
+};
+
+// Same contract as lap_concentrate_slots, for one column per lane (n <= SEG),
+// with the free rows of all the wave's problems inserted in one loop: each
+// pass, every segment that still has a free row takes one Dijkstra step, and a
+// segment whose step reached an unmatched column augments and starts on its
+// next free row while the others go on, so a wave runs as many passes as its
+// busiest problem needs rather than the sum over rows of the busiest problem
+// per row.  The argmin is a ballot of the lanes at the minimum (the lowest
+// such lane is the lowest column), and the matched rows are kept in LDS as row
+// offsets r * n.  The decisions and the arithmetic are those of
+// lap_concentrate_slots.
+template <typename T, int SEG>
+__device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG, 1>& sc, int n,
+                                                       T* __restrict__ R, T* __restrict__ duals,
+                                                       int32_t* __restrict__ assign)
+{
+    using S = SegS<SEG>;
+    using Bits = SegBits<SEG>;
+    constexpr int NONE = 1 << 20;
+    const T* __restrict__ M = sc.M;
+    const int l = S::lane();
+    const bool ok = l < n;
+    const T INF = inf_of<T>();
+
+    // ---- column reduction ---------------------------------------------------
+    T v = 0;
+    int crow = 0;
+    if (ok) {
+        v = M[l];
+        for (int r = 1; r < n; ++r) {
+            const T m = M[r * n + l];
+            if (m < v) {
+                v = m;
+                crow = r;
+            }
+        }
+    }
+    sc.aux[l] = NONE;
+    wave_sync();
+    if (ok) atomicMin(&sc.aux[crow], l);
+    wave_sync();
+    int poff = (ok && sc.aux[crow] == l) ? crow * n : -1;   // offset of the matched row
+    T ucol = 0;
+    sc.p[l] = poff;
+    sc.u[l] = 0.0;
+    unsigned long long freem = Bits::get(ok && sc.aux[l] == NONE);
+    wave_sync();
+
+    // ---- Hungarian method, all problems of the wave together -----------------
+    int row = Bits::first(freem);   // free row being inserted, -1 when done
+    freem &= freem - 1;
+    T dist = INF;
+    int way = -1;
+    bool used = false;
+    int i0n = row >= 0 ? row * n : 0;   // offset of the row being scanned
+    T ui0 = 0;
+    T d0 = 0;
+    int j0 = -1;
+    while (__ballot(row >= 0) != 0) {
+        const bool active = row >= 0;
+        const bool live = active && ok && !used;
+        const T cur = d0 + ((M[i0n + (ok ? l : 0)] - ui0) - v);
+        if (live && cur < dist) {
+            dist = cur;
+            way = j0;
+        }
+        const T lm = live ? dist : INF;
+        const T dmin = S::min(lm);
+        const int j1 = Bits::first(Bits::get(live && lm == dmin));
+        const int jc = j1 >= 0 ? j1 : 0;
+        const int pj = sc.p[jc];
+        const T uj = (T)sc.u[jc];
+        const bool aug = active && (j1 < 0 || pj < 0);
+        used = used || (l == j1);
+        j0 = j1;
+        i0n = pj >= 0 ? pj : 0;
+        ui0 = uj;
+        d0 = dmin;
+        if (__ballot(aug) != 0) {
+            // Dual shift of the scanned tree (the reached column has dist =
+            // dmin, so its shift is 0), predecessors published for the flip.
+            if (aug) {
+                if (used) {
+                    const T sh = dmin - dist;
+                    v -= sh;
+                    ucol += sh;
+                }
+                sc.way[l] = way;
+                sc.u[l] = (double)ucol;
+            }
+            wave_sync();
+            // Flip the path from the reached column back to the new row.
+            int newp = poff;
+            T newu = ucol;
+            if (aug) {
+                for (int j = j1, hop = 0; j >= 0 && hop <= n; ++hop) {
+                    const int w = sc.way[j];
+                    const int wc = w >= 0 ? w : 0;
+                    const int pw = sc.p[wc];
+                    const T uw = (T)sc.u[wc];
+                    if (l == j) {
+                        newp = w >= 0 ? pw : row * n;
+                        newu = w >= 0 ? uw : dmin;
+                    }
+                    j = w;
+                }
+            }
+            wave_sync();
+            if (aug) {
+                poff = newp;
+                ucol = newu;
+                sc.p[l] = poff;
+                sc.u[l] = (double)ucol;
+                row = Bits::first(freem);
+                freem &= freem - 1;
+                dist = INF;
+                way = -1;
+                used = false;
+                i0n = row >= 0 ? row * n : 0;
+                ui0 = 0;
+                d0 = 0;
+                j0 = -1;
+            }
+            wave_sync();
+        }
+    }
+
+    // Row indices for the canonical passes.
+    const int prow = poff >= 0 ? poff / n : -1;
+    sc.p[l] = prow;
+    wave_sync();
+    const T va[1] = {v};
+    const int pa[1] = {prow};
+    const T ua[1] = {ucol};
+    return lap_canonical_finish<T, SEG, 1>(sc, n, R, duals, assign, va, pa, ua);
 }
 
 }  // namespace qap
