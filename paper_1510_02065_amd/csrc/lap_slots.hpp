@@ -84,42 +84,44 @@ struct SegS {
         }
         return x;
     }
-    template <typename T>
-    __device__ __forceinline__ static T sum(T x) {
-        x = x + dpp<kDppXor1>(x);
-        x = x + dpp<kDppXor2>(x);
-        x = x + dpp<kDppHalfMirror>(x);
-        if constexpr (SEG >= 16) x = x + dpp<kDppMirror>(x);
-        if constexpr (SEG >= 32) {
-            T a, b;
-            swap_pair<16>(x, a, b);
-            x = a + b;
-        }
-        if constexpr (SEG >= 64) {
-            T a, b;
-            swap_pair<32>(x, a, b);
-            x = a + b;
-        }
-        return x;
-    }
-    __device__ __forceinline__ static double sum_down(double x) {
-        x = add_down(x, dpp<kDppXor1>(x));
-        x = add_down(x, dpp<kDppXor2>(x));
-        x = add_down(x, dpp<kDppHalfMirror>(x));
-        if constexpr (SEG >= 16) x = add_down(x, dpp<kDppMirror>(x));
-        if constexpr (SEG >= 32) {
-            double a, b;
-            swap_pair<16>(x, a, b);
-            x = add_down(a, b);
-        }
-        if constexpr (SEG >= 64) {
-            double a, b;
-            swap_pair<32>(x, a, b);
-            x = add_down(a, b);
-        }
-        return x;
-    }
 };
+
+// Sum of one value per column over the 64 column slots of a problem, in one
+// fixed order whatever the layout: column l + k*SEG lives in slot k of lane l;
+// pairs at stride 1, 2, 4, ..., 32 are added bottom-up (the segment
+// butterflies give every lane the same bits at each level, since addition is
+// commutative), absent columns count as +0 and the levels above SEG*K add
+// +0 explicitly.  So every (SEG, K) configuration returns the same bits.
+template <int SEG, int K, typename T, typename Add>
+__device__ __forceinline__ T tree_sum64(const T (&x)[K], Add add)
+{
+    constexpr int KP = K <= 1 ? 1 : K <= 2 ? 2 : K <= 4 ? 4 : 8;
+    static_assert(SEG * KP <= 64, "at most 64 column slots");
+    T y[KP];
+    for (int s = 0; s < KP; ++s) y[s] = s < K ? x[s] : T(0);
+    for (int s = 0; s < KP; ++s) {
+        T v = y[s];
+        v = add(v, dpp<kDppXor1>(v));
+        v = add(v, dpp<kDppXor2>(v));
+        v = add(v, dpp<kDppHalfMirror>(v));
+        if constexpr (SEG >= 16) v = add(v, dpp<kDppMirror>(v));
+        if constexpr (SEG >= 32) {
+            T a, b;
+            swap_pair<16>(v, a, b);
+            v = add(a, b);
+        }
+        if constexpr (SEG >= 64) {
+            T a, b;
+            swap_pair<32>(v, a, b);
+            v = add(a, b);
+        }
+        y[s] = v;
+    }
+    for (int st = 1; st < KP; st *= 2)
+        for (int s = 0; s + st < KP; s += 2 * st) y[s] = add(y[s], y[s + st]);
+    for (int w = SEG * KP; w < 64; w *= 2) y[0] = add(y[0], T(0));
+    return y[0];
+}
 
 // Per-segment LDS working set:
 // [matrix n*n of T | p: W ints | aux: W ints | way: W ints | pad |
@@ -157,6 +159,11 @@ struct SlotScratch {
         vb = va + W;
     }
 };
+
+template <typename T, int SEG, int K>
+__device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc, int n, T* __restrict__ R,
+                                               T* __restrict__ duals, int32_t* __restrict__ assign,
+                                               const T (&vc)[K], const T (&ur)[K], const int (&sg)[K]);
 
 // Canonical dual and residual, from the solver's optimal duals and matching:
 // v (column duals) and p (row matched to each column) of this lane's K
@@ -230,7 +237,7 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
 
     // ---- row-canonical point (lanes = rows) ---------------------------------
     // y_r = shortest distance to row r from label -u_r at every row, over
-    // arcs s -> r of reduced cost M[r][sigma(s)] - u_r - v_{sigma(s)} >= 0.
+    // arcs s -> r of reduced cost M[r][sigma(s)] - v_{sigma(s)} - u_r >= 0.
     T y[K];
     {
         bool done[K];
@@ -253,7 +260,7 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
             const T vcs = (T)sc.vb[cs];
             for (int s = 0; s < K; ++s) {
                 done[s] = done[s] || (c[s] == rr);
-                const T nd = dmin + ((M[(ok[s] ? c[s] : 0) * n + cs] - urow[s]) - vcs);
+                const T nd = dmin + ((M[(ok[s] ? c[s] : 0) * n + cs] - vcs) - urow[s]);
                 if (!done[s] && nd < y[s]) y[s] = nd;
             }
         }
@@ -264,6 +271,28 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
     for (int s = 0; s < K; ++s) {
         vc[s] = v[s] + x[s];     // lane as columns
         ur[s] = urow[s] + y[s];  // lane as rows
+    }
+    return lap_complete<T, SEG, K>(sc, n, R, duals, assign, vc, ur, sg);
+}
+
+// From the canonical points to the residual and S: vc (this lane's columns'
+// column-canonical duals), ur (its rows' row-canonical duals) and sg (sigma of
+// its rows, for `assign`).  The other halves of the two points are completed
+// here: u^c_r = min_q (M_rq - v^c_q), v^r_q = min_r (M_rq - u^r_r).
+template <typename T, int SEG, int K>
+__device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc, int n, T* __restrict__ R,
+                                               T* __restrict__ duals, int32_t* __restrict__ assign,
+                                               const T (&vc)[K], const T (&ur)[K], const int (&sg)[K])
+{
+    using S = SegS<SEG>;
+    const T* __restrict__ M = sc.M;
+    const int lane = S::lane();
+    const T INF = inf_of<T>();
+    int c[K];
+    bool ok[K];
+    for (int s = 0; s < K; ++s) {
+        c[s] = s * SEG + lane;
+        ok[s] = c[s] < n;
     }
     wave_sync();
 
@@ -297,8 +326,12 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
                 }
             }
         }
-        T suc = 0, svc = 0, sur = 0, svr = 0;
+        T xuc[K], xvc[K], xur[K], xvr[K];
         for (int s = 0; s < K; ++s) {
+            xuc[s] = ok[s] ? uc[s] : (T)0;
+            xvc[s] = ok[s] ? vc[s] : (T)0;
+            xur[s] = ok[s] ? ur[s] : (T)0;
+            xvr[s] = ok[s] ? vr[s] : (T)0;
             if (!ok[s]) continue;
             if (duals != nullptr) {
                 duals[c[s]] = uc[s];
@@ -307,15 +340,12 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
                 duals[3 * n + c[s]] = vr[s];
             }
             if (assign != nullptr) assign[c[s]] = sg[s];
-            suc += uc[s];
-            svc += vc[s];
-            sur += ur[s];
-            svr += vr[s];
         }
-        suc = S::sum(suc);
-        svc = S::sum(svc);
-        sur = S::sum(sur);
-        svr = S::sum(svr);
+        auto plus = [](T a, T b) { return a + b; };
+        const T suc = tree_sum64<SEG, K>(xuc, plus);
+        const T svc = tree_sum64<SEG, K>(xvc, plus);
+        const T sur = tree_sum64<SEG, K>(xur, plus);
+        const T svr = tree_sum64<SEG, K>(xvr, plus);
         wave_sync();
         return 0.5 * ((suc + svc) + (sur + svr));
     } else {
@@ -352,7 +382,6 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
                     R[r * n + c[s]] = to_float_down(sub_down(sub_down((double)M[r * n + c[s]], V[s]), sc.va[r]));
             }
         }
-        double su = 0.0, sv = 0.0;
         for (int s = 0; s < K; ++s) {
             if (!ok[s]) continue;
             if (duals != nullptr) {
@@ -362,11 +391,10 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
                 duals[3 * n + c[s]] = (T)vr[s];
             }
             if (assign != nullptr) assign[c[s]] = sg[s];
-            su = add_down(su, U[s]);
-            sv = add_down(sv, V[s]);
         }
-        su = S::sum_down(su);
-        sv = S::sum_down(sv);
+        auto down = [](double a, double b) { return add_down(a, b); };
+        const double su = tree_sum64<SEG, K>(U, down);
+        const double sv = tree_sum64<SEG, K>(V, down);
         wave_sync();
         return add_down(su, sv);
     }
@@ -541,6 +569,88 @@ struct SegBits {
     }
 };
 
+// The two canonical passes of lap_canonical_finish side by side, for one
+// column per lane (n <= SEG, SEG >= 16): the first SEG/2 lanes of a segment
+// run the column pass and the other SEG/2 the row pass, each lane holding
+// nodes h and h + SEG/2, so both take n steps together.  A relaxation is
+// written (M - per-step dual) - per-node dual for both passes.  On return
+// (lane as column / as row, K = 1 layout) vc is the column-canonical dual of
+// the lane's column, ur the row-canonical dual of its row and sg its row's
+// column.  Expects sc.p (row of each column) and sc.u (that row's dual).
+template <typename T, int SEG>
+__device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc, int n, T v, int prow, T& vc,
+                                                T& ur, int& sg)
+{
+    static_assert(SEG >= 16, "two half segments of at least 8 lanes");
+    constexpr int H = SEG / 2;
+    using HS = SegS<H>;
+    using HB = SegBits<H>;
+    const T* __restrict__ M = sc.M;
+    const int l = threadIdx.x & (SEG - 1);
+    const T INF = inf_of<T>();
+    // sigma (column of each row) and v in LDS.
+    if (l < n && prow >= 0 && prow < n) sc.aux[prow] = l;
+    sc.vb[l] = (double)v;
+    wave_sync();
+    const bool rowpass = l >= H;
+    const int h = l & (H - 1);
+    int t[2];
+    T lab[2], w[2];
+    bool done[2];
+    for (int q = 0; q < 2; ++q) {
+        t[q] = h + q * H;
+        const bool okn = t[q] < n;
+        const int tc = okn ? t[q] : 0;
+        if (rowpass) {
+            int sgt = sc.aux[tc];
+            sgt = (sgt >= 0 && sgt < n) ? sgt : 0;
+            w[q] = (T)sc.u[sgt];       // u_r of row t: the dual stored at its column
+        } else {
+            w[q] = (T)sc.vb[tc];       // v_q
+        }
+        lab[q] = okn ? -w[q] : INF;
+        done[q] = !okn;
+    }
+    // Relaxation of node t through the node f just fixed:
+    //   column pass: M[p(f)][t] - u(f) - v_t;   row pass: M[t][sigma(f)] - v_sigma(f) - u_t.
+    const int sa = rowpass ? n : 1, sb = rowpass ? 1 : n;
+    for (int step = 0; step < n; ++step) {
+        T lm = done[0] ? INF : lab[0];
+        if (!done[1] && lab[1] < lm) lm = lab[1];
+        const T dmin = HS::min(lm);
+        const unsigned long long b0 = HB::get(!done[0] && lab[0] == dmin);
+        const unsigned long long b1 = HB::get(!done[1] && lab[1] == dmin);
+        const int f = b0 ? HB::first(b0) : (b1 ? HB::first(b1) + H : -1);
+        const int fc = f >= 0 ? f : 0;
+        int key = rowpass ? sc.aux[fc] : sc.p[fc];
+        key = (key >= 0 && key < n) ? key : 0;
+        const T s1 = rowpass ? (T)sc.vb[key] : (T)sc.u[fc];
+        for (int q = 0; q < 2; ++q) {
+            done[q] = done[q] || (t[q] == f);
+            const int tc = t[q] < n ? t[q] : 0;
+            const T nd = dmin + ((M[tc * sa + key * sb] - s1) - w[q]);
+            if (!done[q] && nd < lab[q]) lab[q] = nd;
+        }
+    }
+    wave_sync();
+    // Column pass: v^c = v + x into va; row pass: u^r = u + y into u (the
+    // solver's row duals are no longer needed).
+    for (int q = 0; q < 2; ++q) {
+        if (t[q] < n) {
+            if (rowpass)
+                sc.u[t[q]] = (double)(w[q] + lab[q]);
+            else
+                sc.va[t[q]] = (double)(w[q] + lab[q]);
+        }
+    }
+    wave_sync();
+    const int lc = l < n ? l : 0;
+    vc = (T)sc.va[lc];
+    ur = (T)sc.u[lc];
+    sg = sc.aux[lc];
+    wave_sync();
+}
+
 // Same contract as lap_concentrate_slots, for one column per lane (n <= SEG),
 // with the free rows of all the wave's problems inserted in one loop: each
 // pass, every segment that still has a free row takes one Dijkstra step, and a
@@ -671,10 +781,20 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
     const int prow = poff >= 0 ? poff / n : -1;
     sc.p[l] = prow;
     wave_sync();
-    const T va[1] = {v};
-    const int pa[1] = {prow};
-    const T ua[1] = {ucol};
-    return lap_canonical_finish<T, SEG, 1>(sc, n, R, duals, assign, va, pa, ua);
+    if constexpr (SEG >= 16) {
+        T vc, ur;
+        int sg;
+        canonical_split<T, SEG>(sc, n, v, prow, vc, ur, sg);
+        const T vca[1] = {vc};
+        const T ura[1] = {ur};
+        const int sga[1] = {sg};
+        return lap_complete<T, SEG, 1>(sc, n, R, duals, assign, vca, ura, sga);
+    } else {
+        const T va[1] = {v};
+        const int pa[1] = {prow};
+        const T ua[1] = {ucol};
+        return lap_canonical_finish<T, SEG, 1>(sc, n, R, duals, assign, va, pa, ua);
+    }
 }
 
 }  // namespace qap

@@ -191,3 +191,28 @@ def test_errors():
     with pytest.raises(QapError):
         g.lap_values()   # needs trace_level 2
     assert g.ascend(0) == g.bound()[0]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_slot_configurations_agree_bitwise(tmp_path, precision):
+    # Every (lanes per problem, columns per lane) configuration makes the same
+    # decisions and sums in the same order, so the autotuner's choice never
+    # changes a bit of the state.  The tune cache forces each configuration
+    # on the D and C families (n = 11 and 12 at N = 13).
+    F, D = qapgen.clustered(13, 2)
+    prec = {"fp64": 0, "fp32": 1}[precision]
+    ref = None
+    for seg, k in [(8, 2), (8, 3), (16, 1), (16, 2), (32, 1), (64, 1)]:
+        cache = tmp_path / f"tune_{seg}_{k}.txt"
+        cache.write_text(f"gfx950 prec={prec} fam=0 seg=16 nmax=11|{seg} {k}\n"
+                         f"gfx950 prec={prec} fam=1 seg=16 nmax=12|{seg} {k}\n")
+        print(f"configuration SEG={seg} K={k} {precision}", flush=True)
+        h = Rlt2(F, D, precision=precision, trace_level=2, tune_cache=cache)
+        h.ascend(4)
+        got = (h.trace()[0], *h.read_state()[1:], *h.lap_values()[:2])
+        h.close()
+        if ref is None:
+            ref = got
+        else:
+            for x, y in zip(got, ref):
+                np.testing.assert_array_equal(x, y)
