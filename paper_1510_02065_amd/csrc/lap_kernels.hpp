@@ -21,11 +21,11 @@ struct FamilyClass {
 
 enum : int { kFamD = 0, kFamC = 1 };
 
-// How the D family is stored and enumerated (see half_block).
+// How the D family is stored and enumerated (see pair_block).
 enum : int {
-    kAllBlocks = 0,    // every block stored; problem b is block b, parent c_b
-    kHalfStore = 1,    // one block per complementary pair stored; problem h is
-                       // stored block h, parents c_beta and c_twin
+    kAllBlocks = 0,    // every block stored (block-major); problem b is block b, parent c_b
+    kHalfStore = 1,    // one block per complementary pair stored (pair-major);
+                       // problem h is stored block h, parents c_beta and c_twin
     kHalfStoreTune = 2 // as kHalfStore, parent c_beta only (tuning runs)
 };
 
@@ -47,6 +47,7 @@ __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __res
     const bool active = x < fc.total;
     int n = 0;
     T* blk = nullptr;
+    long long ld = 0;   // row stride of the block in global memory
     long long pidx = 0, pidx2 = -1;
     if (active) {
         const int kk = find_seg(fc.pre, fc.Kc, x);
@@ -54,25 +55,34 @@ __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __res
         const long long b = x - fc.pre[kk];
         if (FAM == kFamD) {
             n = I.N - 2;
-            blk = D + I.offD + b * I.ldD;
-            long long beta = b, tb = -1;
-            if (mode != kAllBlocks) half_block(I.N, b, &beta, &tb);
-            pidx = I.offC + beta;
-            if (mode == kHalfStore) pidx2 = I.offC + tb;
+            if (mode == kAllBlocks) {
+                blk = D + I.offD + b * I.ldD;
+                ld = n;
+                pidx = I.offC + b;
+            } else {
+                long long beta, tb, base;
+                pair_block(I.N, b, &beta, &tb, &base);
+                blk = D + I.offD + base;
+                ld = (long long)I.N * (I.N - 1) * n;
+                pidx = I.offC + beta;
+                if (mode == kHalfStore) pidx2 = I.offC + tb;
+            }
         } else {
             n = I.N - 1;
             blk = C + I.offC + b * (long long)(I.N - 1) * (I.N - 1);
+            ld = n;
             pidx = I.offB + b;
         }
     }
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
-    for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
+    for (int r = 0; r < n; ++r)
+        for (int c = lane; c < n; c += SEG) sc.M[r * n + c] = blk[r * ld + c];
     wave_sync();
     double S;
     if constexpr (K == 1)
-        S = lap_concentrate_flat<T, SEG>(sc, n, active ? blk : nullptr, nullptr, nullptr);
+        S = lap_concentrate_flat<T, SEG>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
     else
-        S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr);
+        S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
     if (active && lane == 0) {
         T* parent = (FAM == kFamD) ? C : B;
         if constexpr (sizeof(T) == 8) {
@@ -114,9 +124,9 @@ __global__ __launch_bounds__(64) void k_lap_B_s(T* __restrict__ B, const Inst* _
     wave_sync();
     double S;
     if constexpr (K == 1)
-        S = lap_concentrate_flat<T, SEG>(sc, n, active ? blk : nullptr, nullptr, nullptr);
+        S = lap_concentrate_flat<T, SEG>(sc, n, active ? blk : nullptr, n, nullptr, nullptr);
     else
-        S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, nullptr, nullptr);
+        S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, n, nullptr, nullptr);
     if (active && lane == 0) {
         const double L = (sizeof(T) == 4) ? add_down(lb[2 * k], S) : lb[2 * k] + S;
         lb[2 * k] = L;

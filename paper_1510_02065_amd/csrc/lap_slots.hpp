@@ -162,7 +162,7 @@ struct SlotScratch {
 
 template <typename T, int SEG, int K>
 __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc, int n, T* __restrict__ R,
-                                               T* __restrict__ duals, int32_t* __restrict__ assign,
+                                               long long ldr, T* __restrict__ duals, int32_t* __restrict__ assign,
                                                const T (&vc)[K], const T (&ur)[K], const int (&sg)[K]);
 
 // Canonical dual and residual, from the solver's optimal duals and matching:
@@ -171,7 +171,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
 // sc.u (row dual per column) hold the same for every column.
 template <typename T, int SEG, int K>
 __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG, K>& sc, int n,
-                                                       T* __restrict__ R, T* __restrict__ duals,
+                                                       T* __restrict__ R, long long ldr, T* __restrict__ duals,
                                                        int32_t* __restrict__ assign, const T (&v)[K],
                                                        const int (&p)[K], const T (&ucol)[K])
 {
@@ -272,7 +272,7 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
         vc[s] = v[s] + x[s];     // lane as columns
         ur[s] = urow[s] + y[s];  // lane as rows
     }
-    return lap_complete<T, SEG, K>(sc, n, R, duals, assign, vc, ur, sg);
+    return lap_complete<T, SEG, K>(sc, n, R, ldr, duals, assign, vc, ur, sg);
 }
 
 // From the canonical points to the residual and S: vc (this lane's columns'
@@ -281,7 +281,7 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
 // here: u^c_r = min_q (M_rq - v^c_q), v^r_q = min_r (M_rq - u^r_r).
 template <typename T, int SEG, int K>
 __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc, int n, T* __restrict__ R,
-                                               T* __restrict__ duals, int32_t* __restrict__ assign,
+                                               long long ldr, T* __restrict__ duals, int32_t* __restrict__ assign,
                                                const T (&vc)[K], const T (&ur)[K], const int (&sg)[K])
 {
     using S = SegS<SEG>;
@@ -322,7 +322,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
                     const T m = M[r * n + c[s]];
                     const T r1 = (m - vc[s]) - (T)sc.va[r];
                     const T r2 = (m - (T)sc.vb[r]) - vr[s];
-                    R[r * n + c[s]] = (T)0.5 * (r1 + r2);
+                    R[r * ldr + c[s]] = (T)0.5 * (r1 + r2);
                 }
             }
         }
@@ -379,7 +379,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             for (int s = 0; s < K; ++s) {
                 if (!ok[s]) continue;
                 for (int r = 0; r < n; ++r)
-                    R[r * n + c[s]] = to_float_down(sub_down(sub_down((double)M[r * n + c[s]], V[s]), sc.va[r]));
+                    R[r * ldr + c[s]] = to_float_down(sub_down(sub_down((double)M[r * n + c[s]], V[s]), sc.va[r]));
             }
         }
         for (int s = 0; s < K; ++s) {
@@ -401,13 +401,14 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
 }
 
 // Solve, canonicalise and write residuals for the n x n matrix sc.M (in LDS,
-// row stride n, left unchanged).  R (nullable) receives the residual, duals
-// (nullable) [uc | vc | ur | vr], assign (nullable) the solver's assignment.
+// row stride n, left unchanged).  R (nullable) receives the residual (row
+// stride ldr), duals (nullable) [uc | vc | ur | vr], assign (nullable) the
+// solver's assignment.
 // Returns S to every lane of the segment.  Called by whole waves; segments may
 // have different n (0 <= n <= SEG*K).
 template <typename T, int SEG, int K>
 __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG, K>& sc, int n,
-                                                        T* __restrict__ R, T* __restrict__ duals,
+                                                        T* __restrict__ R, long long ldr, T* __restrict__ duals,
                                                         int32_t* __restrict__ assign)
 {
     using S = SegS<SEG>;
@@ -547,7 +548,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
         wave_sync();
     }
 
-    return lap_canonical_finish<T, SEG, K>(sc, n, R, duals, assign, v, p, ucol);
+    return lap_canonical_finish<T, SEG, K>(sc, n, R, ldr, duals, assign, v, p, ucol);
 }
 
 // Lane bits of a predicate over this lane's segment (bit 0 = the segment's
@@ -663,7 +664,7 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
 // lap_concentrate_slots.
 template <typename T, int SEG>
 __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG, 1>& sc, int n,
-                                                       T* __restrict__ R, T* __restrict__ duals,
+                                                       T* __restrict__ R, long long ldr, T* __restrict__ duals,
                                                        int32_t* __restrict__ assign)
 {
     using S = SegS<SEG>;
@@ -741,20 +742,24 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
                 sc.u[l] = (double)ucol;
             }
             wave_sync();
-            // Flip the path from the reached column back to the new row.
+            // Flip the path from the reached column back to the new row: a
+            // column on it takes the row and row dual of its predecessor (read
+            // by every lane at once), the first one the new row.  Only the
+            // walk that marks the path is serial.
             int newp = poff;
             T newu = ucol;
             if (aug) {
+                const int wc = way >= 0 ? way : 0;
+                const int pw = sc.p[wc];
+                const T uw = (T)sc.u[wc];
+                bool onpath = false;
                 for (int j = j1, hop = 0; j >= 0 && hop <= n; ++hop) {
-                    const int w = sc.way[j];
-                    const int wc = w >= 0 ? w : 0;
-                    const int pw = sc.p[wc];
-                    const T uw = (T)sc.u[wc];
-                    if (l == j) {
-                        newp = w >= 0 ? pw : row * n;
-                        newu = w >= 0 ? uw : dmin;
-                    }
-                    j = w;
+                    onpath = onpath || (l == j);
+                    j = sc.way[j];
+                }
+                if (onpath) {
+                    newp = way >= 0 ? pw : row * n;
+                    newu = way >= 0 ? uw : dmin;
                 }
             }
             wave_sync();
@@ -788,12 +793,12 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
         const T vca[1] = {vc};
         const T ura[1] = {ur};
         const int sga[1] = {sg};
-        return lap_complete<T, SEG, 1>(sc, n, R, duals, assign, vca, ura, sga);
+        return lap_complete<T, SEG, 1>(sc, n, R, ldr, duals, assign, vca, ura, sga);
     } else {
         const T va[1] = {v};
         const int pa[1] = {prow};
         const T ua[1] = {ucol};
-        return lap_canonical_finish<T, SEG, 1>(sc, n, R, duals, assign, va, pa, ua);
+        return lap_canonical_finish<T, SEG, 1>(sc, n, R, ldr, duals, assign, va, pa, ua);
     }
 }
 

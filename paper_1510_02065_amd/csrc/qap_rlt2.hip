@@ -276,12 +276,25 @@ hipError_t tune_family(qap_rlt2* h, int famk)
         // the parents of the first X half blocks lie at or below the last one's.
         const int mode = h->dmode == qap::kAllBlocks ? qap::kAllBlocks : qap::kHalfStoreTune;
         if (famk == qap::kFamD) {
-            long long pl = bl, twin = 0;
-            if (mode != qap::kAllBlocks) qap::half_block(IL.N, bl, &pl, &twin);
             blk0 = I0.offD;
-            blk1 = IL.offD + (bl + 1) * IL.ldD;
             par0 = I0.offC;
-            par1 = IL.offC + pl + 1;
+            if (mode == qap::kAllBlocks) {
+                blk1 = IL.offD + (bl + 1) * IL.ldD;
+                par1 = IL.offC + bl + 1;
+            } else {
+                // Stored blocks 0..bl lie in the first bl / (N(N-1)) + 1 facility
+                // pairs of the pair-major layout; their parents c_beta anywhere
+                // below the largest beta among them.
+                const long long NL = (long long)IL.N * (IL.N - 1), n2 = IL.N - 2;
+                blk1 = IL.offD + (bl / NL + 1) * n2 * NL * n2;
+                long long pmax = 0;
+                for (long long hb = 0; hb <= bl; ++hb) {
+                    long long beta = 0, twin = 0, base = 0;
+                    qap::pair_block(IL.N, hb, &beta, &twin, &base);
+                    pmax = std::max(pmax, beta);
+                }
+                par1 = IL.offC + pmax + 1;
+            }
             blkbase = static_cast<char*>(h->dD);
             parbase = static_cast<char*>(h->dC);
         } else {
@@ -443,12 +456,13 @@ hipError_t enqueue_step(qap_rlt2* h, int step)
                            h->dInst, h->dPreC, h->K, h->totalC);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        if (h->dmode == qap::kAllBlocks)
-            hipLaunchKernelGGL((qap::k_sweep<T, false>), dim3((unsigned)h->totalWG), dim3(256), 0, st, D, CC, B,
+        if (h->dmode == qap::kAllBlocks) {
+            hipLaunchKernelGGL((qap::k_sweep<T>), dim3((unsigned)h->totalWG), dim3(256), 0, st, D, CC, B,
                                h->dTri, h->dInst, h->dPreWG, h->K, h->totalB);
-        else
-            hipLaunchKernelGGL((qap::k_sweep<T, true>), dim3((unsigned)h->totalWG), dim3(256), 0, st, D, CC, B,
-                               h->dTri, h->dInst, h->dPreWG, h->K, h->totalB);
+            return hipGetLastError();
+        }
+        hipLaunchKernelGGL((qap::k_sweep_cube<T>), dim3((unsigned)h->totalWG), dim3(256), 0, st, D, CC, B,
+                           h->dTri, h->dInst, h->dPreWG, h->K, h->totalB);
         return hipGetLastError();
     }
     case 4:
@@ -677,7 +691,10 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
         qap::Inst& I = h->inst[k];
         I.N = N;
         I.ntri = N * (N - 1) * (N - 2) / 6;
-        I.wpt = (N * n1 * n2 + 255) / 256;
+        // sweep workgroups per facility triple: 4 waves of 4x4x4 location
+        // cubes (one stored block per pair), or 256 groups (every block)
+        const int cubes = ((N + 3) / 4) * ((N + 3) / 4) * ((N + 3) / 4);
+        I.wpt = h->dmode != qap::kAllBlocks ? (cubes + 3) / 4 : (N * n1 * n2 + 255) / 256;
         I.pad_ = 0;
         I.offB = h->totalB;
         I.offC = h->totalC;
@@ -698,7 +715,10 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
         const long long nC = (long long)N * N * n1 * n1;
         h->totalB += (long long)N * N;
         h->totalC += nC;
-        h->totalD += (h->dmode == qap::kAllBlocks ? nC : nC / 2) * I.ldD;
+        if (h->dmode == qap::kAllBlocks)
+            h->totalD += nC * I.ldD;
+        else   // pair-major, one block per pair, unpadded; instances start 128-byte aligned
+            h->totalD += ((nC / 2) * n2 * n2 + align_elems - 1) / align_elems * align_elems;
         h->totalWG += 8LL * ((I.ntri + 7) / 8) * I.wpt;
     }
     // Segment-size classes of the three families.
@@ -1040,15 +1060,20 @@ qap_status qap_rlt2_instance_state(qap_rlt2* h, int k, double* lb, double* B, do
         if (h->dmode == qap::kAllBlocks) {
             QAP_HIP(widen(D, d, blk, I.ldD * h->elem, nC));
         } else {
-            // One stored block per complementary pair: copy both ways.
-            std::vector<double> half((size_t)(nC / 2) * blk);
-            QAP_HIP(widen(half.data(), d, blk, I.ldD * h->elem, nC / 2));
-            double* out = D;
+            // One stored block per complementary pair, pair-major: copy each
+            // row to both blocks of the pair.
+            const long long total = (nC / 2) * blk;
+            std::vector<double> half((size_t)total);
+            QAP_HIP(widen(half.data(), d, total, (size_t)total * h->elem, 1));
+            const long long ld = (long long)N * (N - 1) * n2;
             for (long long hb = 0; hb < nC / 2; ++hb) {
-                long long beta = 0, twin = 0;
-                qap::half_block(N, hb, &beta, &twin);
-                std::copy(half.begin() + hb * blk, half.begin() + (hb + 1) * blk, out + beta * blk);
-                std::copy(half.begin() + hb * blk, half.begin() + (hb + 1) * blk, out + twin * blk);
+                long long beta = 0, twin = 0, base = 0;
+                qap::pair_block(N, hb, &beta, &twin, &base);
+                for (int r = 0; r < n2; ++r) {
+                    const double* src = half.data() + base + r * ld;
+                    std::copy(src, src + n2, D + beta * blk + r * n2);
+                    std::copy(src, src + n2, D + twin * blk + r * n2);
+                }
             }
         }
     }

@@ -104,49 +104,55 @@ __device__ __forceinline__ int64_t beta_of(int N, int a, int la, int b, int lb) 
 // same six-way group of equation (11).  The six-way transfer leaves every
 // member of a group with the same value and a concentration leaves both blocks
 // with the same residual, so from D = 0 on the two blocks are always equal:
-// the handle stores one copy, the block with a < b.  Half index h in
-// [0, N^2 (N-1)^2 / 2) lists those blocks in block order (a, la, b, lb).
+// the handle can store one copy, the block with a < b.
 //
-// half_block: *beta gets the block number (position of its c in C) of half
-// index h and *twin that of its complement.  beta grows with h, so the blocks
-// of half indices 0..h all lie at or below *beta.
-__host__ __device__ __forceinline__ void half_block(int N, long long h, long long* beta, long long* twin)
+// Pair-major layout of those stored blocks.  Row c of block (a,la,b,lb)
+// (facility c not in {a, b}) holds the entries whose six-way groups belong to
+// facility triple {a, b, c}, so the layout keeps, for each facility pair
+// a < b and each row c, the rows of all N (N-1) location pairs (la, lb)
+// together:
+//   offset = ((P(a,b) (N-2) + c') N(N-1) + L(la,lb)) (N-2) + lc',
+// P(a,b) the lexicographic index of the pair, c' = c - [c > a] - [c > b],
+// L(la,lb) = la (N-1) + lb - [lb > la], lc' the compact column.  The steps
+// 1-3 pass over triple {x < y < z} then reads three contiguous runs of
+// N (N-1) (N-2) entries, and an assignment problem reads its block as N-2
+// rows, N (N-1) (N-2) entries apart.
+
+__host__ __device__ __forceinline__ long long pair_index(int N, int a, int b)   // a < b
+{
+    return (long long)a * (2 * N - a - 1) / 2 + (b - a - 1);
+}
+
+// Offset of row c' (compact) of stored block (a, la, b, lb), a < b.
+__host__ __device__ __forceinline__ long long pair_row(int N, int a, int la, int b, int lb, int cq)
+{
+    const long long NL = (long long)N * (N - 1);
+    const int n2 = N - 2;
+    return ((pair_index(N, a, b) * n2 + cq) * NL + (long long)la * (N - 1) + (lb - (lb > la))) * n2;
+}
+
+// Stored block number h in [0, N^2 (N-1)^2 / 2) = P(a,b) N(N-1) + L(la,lb):
+// *beta gets the block number (position of its c in C), *twin that of its
+// complement and *base the offset of its first row (rows are
+// N (N-1) (N-2) apart).
+__host__ __device__ __forceinline__ void pair_block(int N, long long h, long long* beta, long long* twin,
+                                                    long long* base)
 {
     const int n1 = N - 1;
+    const long long NL = (long long)N * n1;
+    long long P = h / NL;
+    const int L = (int)(h - P * NL);
+    *base = P * (N - 2) * NL * (N - 2) + (long long)L * (N - 2);
     int a = 0;
-    long long per = (long long)N * n1 * n1;   // half blocks with this a: N (N-1-a) (N-1)
-    while (h >= per) {
-        h -= per;
+    while (P >= n1 - a) {
+        P -= n1 - a;
         ++a;
-        per -= (long long)N * n1;
     }
-    const long long w = (long long)(n1 - a) * n1;   // blocks of super-block (a, la) with b > a
-    const int la = (int)(h / w);
-    const long long r = h - (long long)la * w;
-    const int bq = a + (int)(r / n1);                // compact b (b > a, so b = bq + 1)
-    const int lq = (int)(r % n1);
-    const int b = bq + 1, lb = lq + (lq >= la);
-    *beta = ((long long)(a * N + la) * n1 + bq) * n1 + lq;
+    const int b = a + 1 + (int)P;
+    const int la = L / n1, lq = L % n1;
+    const int lb = lq + (lq >= la);
+    *beta = ((long long)(a * N + la) * n1 + (b - 1)) * n1 + lq;
     *twin = ((long long)(b * N + lb) * n1 + a) * n1 + (la - (la > lb));
-}
-
-// Half index of D_{(a,la),(b,lb)} for a < b (the inverse of half_block).
-__host__ __device__ __forceinline__ long long half_index(int N, int a, int la, int b, int lb)
-{
-    const long long n1 = N - 1;
-    const long long before = (long long)N * n1 * ((long long)a * n1 - (long long)a * (a - 1) / 2);
-    return before + (long long)la * (n1 - a) * n1 + (long long)(b - 1 - a) * n1 + (lb - (lb > la));
-}
-
-// Half index of the stored copy of block beta (either member of its pair).
-__host__ __device__ __forceinline__ long long half_of_beta(int N, long long beta)
-{
-    const long long n1 = N - 1;
-    const int ln = (int)(beta % n1), kq = (int)((beta / n1) % n1);
-    const int ij = (int)(beta / (n1 * n1));
-    const int a = ij / N, la = ij % N;
-    const int b = kq + (kq >= a), lb = ln + (ln >= la);
-    return a < b ? half_index(N, a, la, b, lb) : half_index(N, b, lb, a, la);
 }
 
 // Offset of d_{(a,la),(b,lb),(c,lc)} inside block beta_of(a,la,b,lb).
@@ -261,15 +267,9 @@ __global__ __launch_bounds__(256) void k_spread_prep(T* __restrict__ C, const T*
 // t mod 8 and consecutive among that XCD's ids, so one XCD works through a
 // triple's six sub-arrays (6 N(N-1)(N-2) entries) together and the partially
 // used cache lines of the four strided members meet in its L2.
-// The first totalB threads of the grid also clear B.
-//
-// HALF: only the block with the smaller facility of each complementary pair
-// is stored (half_index).  As i < k < p, members (P1 P2 P3) and (P2 P1 P3)
-// share the stored entry A, (P1 P3 P2) and (P3 P1 P2) share B, and
-// (P2 P3 P1) and (P3 P2 P1) share C; each member still gets its own block's
-// spread share, in the same order, so the sum has the same bits as with
-// every block stored.
-template <typename T, bool HALF>
+// The first totalB threads of the grid also clear B.  Used when every block
+// is stored; see k_sweep_cube for one block per complementary pair.
+template <typename T>
 __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __restrict__ CC,
                                                T* __restrict__ B, const int* __restrict__ tri,
                                                const Inst* __restrict__ inst,
@@ -302,22 +302,12 @@ __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __re
     const int64_t b0 = beta_of(N, i, j, k, n), b1 = beta_of(N, i, j, p, q);
     const int64_t b2 = beta_of(N, k, n, i, j), b3 = beta_of(N, k, n, p, q);
     const int64_t b4 = beta_of(N, p, q, i, j), b5 = beta_of(N, p, q, k, n);
-    int64_t a0, a1, a2, a3, a4, a5;
-    if constexpr (HALF) {
-        a0 = half_index(N, i, j, k, n) * ldD + entry_of(N, i, j, k, n, p, q);
-        a1 = half_index(N, i, j, p, q) * ldD + entry_of(N, i, j, p, q, k, n);
-        a3 = half_index(N, k, n, p, q) * ldD + entry_of(N, k, n, p, q, i, j);
-        a2 = a0;
-        a4 = a1;
-        a5 = a3;
-    } else {
-        a0 = b0 * ldD + entry_of(N, i, j, k, n, p, q);
-        a1 = b1 * ldD + entry_of(N, i, j, p, q, k, n);
-        a2 = b2 * ldD + entry_of(N, k, n, i, j, p, q);
-        a3 = b3 * ldD + entry_of(N, k, n, p, q, i, j);
-        a4 = b4 * ldD + entry_of(N, p, q, i, j, k, n);
-        a5 = b5 * ldD + entry_of(N, p, q, k, n, i, j);
-    }
+    const int64_t a0 = b0 * ldD + entry_of(N, i, j, k, n, p, q);
+    const int64_t a1 = b1 * ldD + entry_of(N, i, j, p, q, k, n);
+    const int64_t a2 = b2 * ldD + entry_of(N, k, n, i, j, p, q);
+    const int64_t a3 = b3 * ldD + entry_of(N, k, n, p, q, i, j);
+    const int64_t a4 = b4 * ldD + entry_of(N, p, q, i, j, k, n);
+    const int64_t a5 = b5 * ldD + entry_of(N, p, q, k, n, i, j);
 
     T mean;
     if constexpr (sizeof(T) == 8) {
@@ -350,12 +340,93 @@ __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __re
     }
     Dk[a0] = mean;
     Dk[a1] = mean;
+    Dk[a2] = mean;
     Dk[a3] = mean;
-    if constexpr (!HALF) {
-        Dk[a2] = mean;
-        Dk[a4] = mean;
-        Dk[a5] = mean;
+    Dk[a4] = mean;
+    Dk[a5] = mean;
+}
+
+// Steps 1-3 with one stored block per complementary pair (pair_row).  As
+// i < k < p, members (P1 P2 P3) and (P2 P1 P3) share one stored entry A,
+// (P1 P3 P2) and (P3 P1 P2) share B, and (P2 P3 P1) and (P3 P2 P1) share C;
+// each member still gets its own block's spread share, in k_sweep's order,
+// so the sum has the same bits as with every block stored.  Each wave takes a
+// 4 x 4 x 4 cube of location triples (j, n, q) instead of 64 consecutive q:
+//   A = D_{(i,j),(k,n)}[p][q]  (contiguous over q),
+//   B = D_{(i,j),(p,q)}[k][n]  (contiguous over n),
+//   C = D_{(k,n),(p,q)}[i][j]  (contiguous over j),
+// each in the triple's own run of the pair-major layout.  With 4 values along
+// every axis each member's 64 lanes fall on 16 runs of 4 consecutive entries.
+// The cubes of one facility triple are consecutive waves of workgroups on one
+// XCD (as in k_sweep), so the cubes that share lines meet in its L2, and the
+// triple's three runs are read and written once from HBM.  Groups with a repeated location and
+// cube cells past N are masked off.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep_cube(T* __restrict__ Dd, const T* __restrict__ CC,
+                                                    T* __restrict__ B, const int* __restrict__ tri,
+                                                    const Inst* __restrict__ inst,
+                                                    const long long* __restrict__ preWG, int K, long long totalB)
+{
+    const long long gx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gx < totalB) B[gx] = (T)0;
+    const Inst I = inst[find_seg(preWG, K, (long long)blockIdx.x)];
+    const int lbk = (int)((long long)blockIdx.x - I.wg0);
+    const int xcd = lbk & 7;
+    const int local = lbk >> 3;
+    const int t = (local / I.wpt) * 8 + xcd;
+    if (t >= I.ntri) return;
+    const int N = I.N;
+    const int nt = (N + 3) >> 2;                       // cube tiles per axis
+    const int cube = (local % I.wpt) * 4 + (int)(threadIdx.x >> 6);
+    if (cube >= nt * nt * nt) return;
+    const int lane = threadIdx.x & 63;
+    const int tq = cube % nt, tn = (cube / nt) % nt, tj = cube / (nt * nt);
+    const int j = tj * 4 + (lane >> 4), n = tn * 4 + ((lane >> 2) & 3), q = tq * 4 + (lane & 3);
+    if (j >= N || n >= N || q >= N || j == n || j == q || n == q) return;
+    const int* tr = tri + I.tri0 + 3 * t;
+    const int i = tr[0], k = tr[1], p = tr[2];
+    T* __restrict__ Dk = Dd + I.offD;
+    const T* __restrict__ CCk = CC + I.offC;
+
+    const int64_t b0 = beta_of(N, i, j, k, n), b1 = beta_of(N, i, j, p, q);
+    const int64_t b2 = beta_of(N, k, n, i, j), b3 = beta_of(N, k, n, p, q);
+    const int64_t b4 = beta_of(N, p, q, i, j), b5 = beta_of(N, p, q, k, n);
+    const int64_t aA = pair_row(N, i, j, k, n, p - 2) + drop2(q, min(j, n), max(j, n));
+    const int64_t aB = pair_row(N, i, j, p, q, k - 1) + drop2(n, min(j, q), max(j, q));
+    const int64_t aC = pair_row(N, k, n, p, q, i) + drop2(j, min(n, q), max(n, q));
+    const T A0 = Dk[aA], B0 = Dk[aB], C0 = Dk[aC];
+    T mean;
+    if constexpr (sizeof(T) == 8) {
+        const T m0 = A0 + CCk[b0];
+        const T m1 = B0 + CCk[b1];
+        const T m2 = A0 + CCk[b2];
+        const T m3 = C0 + CCk[b3];
+        const T m4 = B0 + CCk[b4];
+        const T m5 = C0 + CCk[b5];
+        T sum = m0;
+        sum += m1;
+        sum += m2;
+        sum += m3;
+        sum += m4;
+        sum += m5;
+        mean = sum / (T)6;
+    } else {
+        double sum = add_down((double)A0, (double)CCk[b0]);
+        sum = add_down(sum, (double)B0);
+        sum = add_down(sum, (double)CCk[b1]);
+        sum = add_down(sum, (double)A0);
+        sum = add_down(sum, (double)CCk[b2]);
+        sum = add_down(sum, (double)C0);
+        sum = add_down(sum, (double)CCk[b3]);
+        sum = add_down(sum, (double)B0);
+        sum = add_down(sum, (double)CCk[b4]);
+        sum = add_down(sum, (double)C0);
+        sum = add_down(sum, (double)CCk[b5]);
+        mean = to_float_down(div_down(sum, 6.0));
     }
+    Dk[aA] = mean;
+    Dk[aB] = mean;
+    Dk[aC] = mean;
 }
 
 // Step 5: the complementary pair c_ijkn, c_knij (equation (10)) both become
@@ -406,17 +477,20 @@ __global__ __launch_bounds__(256) void k_cert_D(const T* __restrict__ Dd, const 
     const int lane = threadIdx.x & 63;
     if (x >= (HALF ? totalC / 2 : totalC)) return;
     const Inst I = inst[find_seg(preC, K, HALF ? 2 * x : x)];
-    const int N = I.N, blk = (N - 2) * (N - 2);
+    const int N = I.N, n2 = N - 2, blk = n2 * n2;
     const long long local = x - (HALF ? I.offC / 2 : I.offC);
-    const T* __restrict__ Db = Dd + I.offD + local * I.ldD;
+    long long beta = local, twin = -1, base = local * I.ldD, ld = n2;
+    if constexpr (HALF) {
+        pair_block(N, local, &beta, &twin, &base);
+        ld = (long long)N * (N - 1) * n2;
+    }
+    const T* __restrict__ Db = Dd + I.offD + base;
     double m = 0.0;
-    for (int e = lane; e < blk; e += 64) m = __builtin_fmin(m, (double)Db[e]);
+    for (int e = lane; e < blk; e += 64) m = __builtin_fmin(m, (double)Db[(e / n2) * ld + e % n2]);
     for (int off = 32; off > 0; off >>= 1) m = __builtin_fmin(m, __shfl_xor(m, off, 64));
     if (lane == 0) {
         const double md = mul_down((double)(N - 2), m);
         if constexpr (HALF) {
-            long long beta, twin;
-            half_block(N, local, &beta, &twin);
             ct[I.offC + beta] = add_down((double)C[I.offC + beta], md);
             ct[I.offC + twin] = add_down((double)C[I.offC + twin], md);
         } else {
