@@ -75,8 +75,11 @@ __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __res
         }
     }
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
-    for (int r = 0; r < n; ++r)
-        for (int c = lane; c < n; c += SEG) sc.M[r * n + c] = blk[r * ld + c];
+    {
+        const T* row = blk;
+        for (int r = 0; r < n; ++r, row += ld)
+            for (int c = lane; c < n; c += SEG) sc.M[r * n + c] = row[c];
+    }
     wave_sync();
     double S;
     if constexpr (K == 1)

@@ -318,11 +318,12 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
         if (R != nullptr) {
             for (int s = 0; s < K; ++s) {
                 if (!ok[s]) continue;
-                for (int r = 0; r < n; ++r) {
+                T* Rr = R + c[s];
+                for (int r = 0; r < n; ++r, Rr += ldr) {
                     const T m = M[r * n + c[s]];
                     const T r1 = (m - vc[s]) - (T)sc.va[r];
                     const T r2 = (m - (T)sc.vb[r]) - vr[s];
-                    R[r * ldr + c[s]] = (T)0.5 * (r1 + r2);
+                    *Rr = (T)0.5 * (r1 + r2);
                 }
             }
         }
@@ -378,8 +379,9 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
         if (R != nullptr) {
             for (int s = 0; s < K; ++s) {
                 if (!ok[s]) continue;
-                for (int r = 0; r < n; ++r)
-                    R[r * ldr + c[s]] = to_float_down(sub_down(sub_down((double)M[r * n + c[s]], V[s]), sc.va[r]));
+                T* Rr = R + c[s];
+                for (int r = 0; r < n; ++r, Rr += ldr)
+                    *Rr = to_float_down(sub_down(sub_down((double)M[r * n + c[s]], V[s]), sc.va[r]));
             }
         }
         for (int s = 0; s < K; ++s) {

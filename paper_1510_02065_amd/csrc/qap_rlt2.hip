@@ -739,15 +739,27 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
     }
 
     // LDS a workgroup may request, and the default configuration of every
-    // class: the most problems per wave that fit.
+    // class: the most problems per wave that fit (families D and C).
     {
         int lim = 0;
         if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && lim > 0)
             h->lds_limit = (size_t)lim;
     }
+    // The B family (one problem per instance) is latency-bound: one column per
+    // lane, the smallest segment that holds the problem.
+    for (ClassHost& c : h->fam[2]) {
+        if (c.total <= 0) continue;
+        const int seg = c.nmax <= 8 ? 8 : c.nmax <= 16 ? 16 : c.nmax <= 32 ? 32 : 64;
+        const size_t need = h->precision == QAP_FP64 ? slot_lds_any<double>(seg, 1, c.nmax)
+                                                     : slot_lds_any<float>(seg, 1, c.nmax);
+        if (need <= h->lds_limit) {
+            c.seg_run = seg;
+            c.k_run = 1;
+        }
+    }
     for (auto& f : h->fam)
         for (ClassHost& c : f) {
-            if (c.total <= 0) continue;
+            if (c.total <= 0 || c.seg_run != 0) continue;
             for (int seg : {8, 16, 32, 64}) {
                 const int k = (c.nmax + seg - 1) / seg;
                 if (!slot_cfg_allowed(seg, k)) continue;

@@ -138,17 +138,19 @@ __host__ __device__ __forceinline__ long long pair_row(int N, int a, int la, int
 __host__ __device__ __forceinline__ void pair_block(int N, long long h, long long* beta, long long* twin,
                                                     long long* base)
 {
+    // h < N^2 (N-1)^2 / 2 < 2^23 for N <= 64: 32-bit arithmetic
     const int n1 = N - 1;
-    const long long NL = (long long)N * n1;
-    long long P = h / NL;
-    const int L = (int)(h - P * NL);
-    *base = P * (N - 2) * NL * (N - 2) + (long long)L * (N - 2);
+    const int NL = N * n1;
+    const int hh = (int)h;
+    int P = hh / NL;
+    const int L = hh - P * NL;
+    *base = ((long long)P * (N - 2) * NL + L) * (N - 2);
     int a = 0;
     while (P >= n1 - a) {
         P -= n1 - a;
         ++a;
     }
-    const int b = a + 1 + (int)P;
+    const int b = a + 1 + P;
     const int la = L / n1, lq = L % n1;
     const int lb = lq + (lq >= la);
     *beta = ((long long)(a * N + la) * n1 + (b - 1)) * n1 + lq;
