@@ -134,9 +134,10 @@ qap_status qap_rlt2_ascend(qap_rlt2* h, int iters, double* bound);
 
 /* Run a single step of the loop body above, for inspection.  Steps 1-3 run
  * as one fused pass: step must be 3 (steps 1-3), 4, 5, 6 or 7 (steps 7-8).
- * Steps 3-6 only enqueue their kernels on the handle's stream and return;
- * step 7 blocks until the iteration is done and records it in the trace.
- * A fault in an enqueued kernel surfaces at the next blocking call. */
+ * Every step only enqueues its kernels on the handle's stream and returns;
+ * step 7 counts the iteration, whose trace entry reaches the host at the
+ * next call that reads the trace or runs qap_rlt2_ascend.  A fault in an
+ * enqueued kernel surfaces at the next blocking call. */
 qap_status qap_rlt2_step(qap_rlt2* h, int step);
 
 /* Certified bound, FP64: with m(beta) the minimum of block D_beta,

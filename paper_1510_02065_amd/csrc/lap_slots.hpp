@@ -558,7 +558,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
 template <int SEG>
 struct SegBits {
     __device__ __forceinline__ static unsigned long long get(bool pred) {
-        const unsigned long long b = __ballot(pred);
+        const unsigned long long b = ballot64(pred);
         if constexpr (SEG == 64)
             return b;
         else
@@ -711,7 +711,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
     T ui0 = 0;
     T d0 = 0;
     int j0 = -1;
-    while (__ballot(row >= 0) != 0) {
+    while (ballot64(row >= 0) != 0) {
         const bool active = row >= 0;
         const bool live = active && ok && !used;
         const T cur = d0 + ((M[i0n + (ok ? l : 0)] - ui0) - v);
@@ -731,7 +731,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
         i0n = pj >= 0 ? pj : 0;
         ui0 = uj;
         d0 = dmin;
-        if (__ballot(aug) != 0) {
+        if (ballot64(aug) != 0) {
             // Dual shift of the scanned tree (the reached column has dist =
             // dmin, so its shift is 0), predecessors published for the flip.
             if (aug) {

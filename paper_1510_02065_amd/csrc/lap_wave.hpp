@@ -37,6 +37,10 @@
 
 namespace qap {
 
+// Wave-wide ballot of a predicate; taking a bool (not an int as __ballot
+// does) lets the compiler use the comparison's lane mask directly.
+__device__ __forceinline__ unsigned long long ballot64(bool pred) { return __builtin_amdgcn_ballot_w64(pred); }
+
 template <typename T> __device__ __forceinline__ T inf_of();
 template <> __device__ __forceinline__ double inf_of<double>() { return __builtin_huge_val(); }
 template <> __device__ __forceinline__ float inf_of<float>() { return __builtin_huge_valf(); }
@@ -182,7 +186,7 @@ struct Seg {
     };
     // lowest lane of each segment with pred true (SEG if none).
     __device__ __forceinline__ static Idx first(bool pred) {
-        const unsigned long long m = __ballot(pred);
+        const unsigned long long m = ballot64(pred);
         Idx r;
 #pragma unroll
         for (int g = 0; g < LPW; ++g) {

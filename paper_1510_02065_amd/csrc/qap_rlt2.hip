@@ -76,6 +76,7 @@ struct qap_rlt2 {
     int trace_level = 1;
     int use_graph = 1;
     int autotune = 1;
+    long long pending = 0;   // iterations of qap_rlt2_step whose trace entries are still on the device
     int dmode = qap::kHalfStore;   // D storage and enumeration (kAllBlocks or kHalfStore)
     bool tuned = false;
     size_t lds_limit = 65536;   // dynamic LDS a workgroup may request
@@ -856,11 +857,27 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
     return QAP_OK;
 }
 
+// Move the trace entries of iterations run by qap_rlt2_step to the host.
+qap_status flush_steps(qap_rlt2* h)
+{
+    if (h->pending == 0) return QAP_OK;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return mark_broken(h, e, "hipStreamSynchronize");
+    qap_status st = drain_trace(h);
+    if (st != QAP_OK) {
+        h->broken = true;
+        return st;
+    }
+    h->pending = 0;
+    return QAP_OK;
+}
+
 qap_status qap_rlt2_ascend(qap_rlt2* h, int iters, double* bound)
 {
     qap_status st = check_handle(h);
     if (st != QAP_OK) return st;
     if (iters < 0) return fail(QAP_EINVAL, "iters must be >= 0");
+    if ((st = flush_steps(h)) != QAP_OK) return st;
     int left = iters;
     if (left > 0 && h->autotune && !h->tuned) {
         hipError_t e = tuned_first_iteration(h);
@@ -931,11 +948,10 @@ qap_status qap_rlt2_step(qap_rlt2* h, int step)
     hipError_t e = enqueue_step_any(h, step);
     if (e != hipSuccess) return mark_broken(h, e, "kernel launch");
     if (step == 7) {
-        e = hipStreamSynchronize(h->stream);
-        if (e != hipSuccess) return mark_broken(h, e, "hipStreamSynchronize");
         h->iterations += 1;
-        st = drain_trace(h);
-        if (st != QAP_OK) return st;
+        // The trace entry stays on the device until a call reads the trace
+        // or the device buffer is full.
+        if (++h->pending >= kTraceCap) return flush_steps(h);
     }
     return QAP_OK;
 }
@@ -1001,6 +1017,10 @@ qap_status qap_rlt2_instance_trace(qap_rlt2* h, int k, int64_t capacity, int64_t
                                    double* lbprime)
 {
     if (!h) return fail(QAP_EINVAL, "null handle");
+    if (!h->broken && h->pending > 0) {
+        qap_status st = flush_steps(h);
+        if (st != QAP_OK) return st;
+    }
     if (k < 0 || k >= h->K) return fail(QAP_EINVAL, "instance index out of range");
     if (capacity < 0) return fail(QAP_EINVAL, "negative capacity");
     const int64_t n = (int64_t)h->tLB[k].size();

@@ -377,9 +377,10 @@ __global__ __launch_bounds__(256) void k_sweep_cube(T* __restrict__ Dd, const T*
     const int local = lbk >> 3;
     const int t = (local / I.wpt) * 8 + xcd;
     if (t >= I.ntri) return;
-    const int N = I.N;
+    const int N = I.N, n1 = N - 1, n2 = N - 2;
     const int nt = (N + 3) >> 2;                       // cube tiles per axis
-    const int cube = (local % I.wpt) * 4 + (int)(threadIdx.x >> 6);
+    // the wave's cube and triple are wave-uniform: keep them scalar
+    const int cube = __builtin_amdgcn_readfirstlane((local % I.wpt) * 4 + (int)(threadIdx.x >> 6));
     if (cube >= nt * nt * nt) return;
     const int lane = threadIdx.x & 63;
     const int tq = cube % nt, tn = (cube / nt) % nt, tj = cube / (nt * nt);
@@ -390,12 +391,27 @@ __global__ __launch_bounds__(256) void k_sweep_cube(T* __restrict__ Dd, const T*
     T* __restrict__ Dk = Dd + I.offD;
     const T* __restrict__ CCk = CC + I.offC;
 
-    const int64_t b0 = beta_of(N, i, j, k, n), b1 = beta_of(N, i, j, p, q);
-    const int64_t b2 = beta_of(N, k, n, i, j), b3 = beta_of(N, k, n, p, q);
-    const int64_t b4 = beta_of(N, p, q, i, j), b5 = beta_of(N, p, q, k, n);
-    const int64_t aA = pair_row(N, i, j, k, n, p - 2) + drop2(q, min(j, n), max(j, n));
-    const int64_t aB = pair_row(N, i, j, p, q, k - 1) + drop2(n, min(j, q), max(j, q));
-    const int64_t aC = pair_row(N, k, n, p, q, i) + drop2(j, min(n, q), max(n, q));
+    // Block numbers of the six members (beta_of with i < k < p worked out):
+    // beta(a, la, b, lb) = a N (N-1)^2 + la (N-1)^2 + b' (N-1) + lb'.
+    const int sq = n1 * n1;
+    const int jn = n - (n > j), jq = q - (q > j), nj = j - (j > n), nq = q - (q > n), qj = j - (j > q),
+              qn = n - (n > q);
+    const int64_t b0 = (int64_t)(i * N) * sq + j * sq + (k - 1) * n1 + jn;
+    const int64_t b1 = (int64_t)(i * N) * sq + j * sq + (p - 1) * n1 + jq;
+    const int64_t b2 = (int64_t)(k * N) * sq + n * sq + i * n1 + nj;
+    const int64_t b3 = (int64_t)(k * N) * sq + n * sq + (p - 1) * n1 + nq;
+    const int64_t b4 = (int64_t)(p * N) * sq + q * sq + i * n1 + qj;
+    const int64_t b5 = (int64_t)(p * N) * sq + q * sq + k * n1 + qn;
+    // The three stored entries (pair_row worked out): each role's run of
+    // the triple starts at a wave-uniform offset; within it, row L(la, lb)
+    // and the compact column.
+    const long long NL = (long long)N * n1;
+    const long long rA = (pair_index(N, i, k) * n2 + (p - 2)) * NL * n2;
+    const long long rB = (pair_index(N, i, p) * n2 + (k - 1)) * NL * n2;
+    const long long rC = (pair_index(N, k, p) * n2 + i) * NL * n2;
+    const int64_t aA = rA + ((j * n1 + jn) * n2 + (jq - (q > n)));
+    const int64_t aB = rB + ((j * n1 + jq) * n2 + (jn - (n > q)));
+    const int64_t aC = rC + ((n * n1 + nq) * n2 + (nj - (j > q)));
     const T A0 = Dk[aA], B0 = Dk[aB], C0 = Dk[aC];
     T mean;
     if constexpr (sizeof(T) == 8) {
