@@ -78,6 +78,7 @@ struct qap_rlt2 {
     int autotune = 1;
     long long pending = 0;   // iterations of qap_rlt2_step whose trace entries are still on the device
     int dmode = qap::kHalfStore;   // D storage and enumeration (kAllBlocks or kHalfStore)
+    int Nmax = 0;                  // largest instance
     bool tuned = false;
     size_t lds_limit = 65536;   // dynamic LDS a workgroup may request
     std::string tune_cache;
@@ -462,8 +463,13 @@ hipError_t enqueue_step(qap_rlt2* h, int step)
                                h->dTri, h->dInst, h->dPreWG, h->K, h->totalB);
             return hipGetLastError();
         }
-        hipLaunchKernelGGL((qap::k_sweep_cube<T>), dim3((unsigned)h->totalWG), dim3(256), 0, st, D, CC, B,
-                           h->dTri, h->dInst, h->dPreWG, h->K, h->totalB);
+        const size_t lds = (size_t)6 * h->Nmax * h->Nmax * sizeof(T);
+        if (lds <= h->lds_limit)
+            hipLaunchKernelGGL((qap::k_sweep_cube<T, true>), dim3((unsigned)h->totalWG), dim3(256), lds, st, D, CC,
+                               B, h->dTri, h->dInst, h->dPreWG, h->K, h->totalB, h->Nmax);
+        else
+            hipLaunchKernelGGL((qap::k_sweep_cube<T, false>), dim3((unsigned)h->totalWG), dim3(256), 0, st, D, CC,
+                               B, h->dTri, h->dInst, h->dPreWG, h->K, h->totalB, h->Nmax);
         return hipGetLastError();
     }
     case 4:
@@ -685,6 +691,7 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
 
     // Packed layout of all instances.
     const long long align_elems = 128 / (long long)h->elem;
+    for (int k = 0; k < count; ++k) h->Nmax = std::max(h->Nmax, (int)Ns[k]);
     std::vector<int> tri;
     h->inst.resize(count);
     for (int k = 0; k < count; ++k) {
@@ -692,10 +699,9 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
         qap::Inst& I = h->inst[k];
         I.N = N;
         I.ntri = N * (N - 1) * (N - 2) / 6;
-        // sweep workgroups per facility triple: 4 waves of 4x4x4 location
-        // cubes (one stored block per pair), or 256 groups (every block)
-        const int cubes = ((N + 3) / 4) * ((N + 3) / 4) * ((N + 3) / 4);
-        I.wpt = h->dmode != qap::kAllBlocks ? (cubes + 3) / 4 : (N * n1 * n2 + 255) / 256;
+        // sweep workgroups per facility triple: kSweepParts (one stored block
+        // per pair), or one per 256 groups (every block)
+        I.wpt = h->dmode != qap::kAllBlocks ? qap::kSweepParts : (N * n1 * n2 + 255) / 256;
         I.pad_ = 0;
         I.offB = h->totalB;
         I.offC = h->totalC;

@@ -352,99 +352,148 @@ __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __re
 // i < k < p, members (P1 P2 P3) and (P2 P1 P3) share one stored entry A,
 // (P1 P3 P2) and (P3 P1 P2) share B, and (P2 P3 P1) and (P3 P2 P1) share C;
 // each member still gets its own block's spread share, in k_sweep's order,
-// so the sum has the same bits as with every block stored.  Each wave takes a
-// 4 x 4 x 4 cube of location triples (j, n, q) instead of 64 consecutive q:
+// so the sum has the same bits as with every block stored.
+//
+// Workgroups: kSweepParts per facility triple, on one XCD (ids congruent to
+// the triple mod 8, as in k_sweep, so lines shared between them meet in that
+// XCD's L2).  A workgroup first stages the six N x N tables of spread shares
+// of its triple in LDS (X[m][a][b] = CC of block (f1, a, f2, b) for the six
+// ordered facility pairs), so the groups read them from LDS instead of
+// making scattered L2 requests.  Each wave then takes 4 x 4 x 4 cubes of
+// location triples (j, n, q), two at a time:
 //   A = D_{(i,j),(k,n)}[p][q]  (contiguous over q),
 //   B = D_{(i,j),(p,q)}[k][n]  (contiguous over n),
 //   C = D_{(k,n),(p,q)}[i][j]  (contiguous over j),
-// each in the triple's own run of the pair-major layout.  With 4 values along
-// every axis each member's 64 lanes fall on 16 runs of 4 consecutive entries.
-// The cubes of one facility triple are consecutive waves of workgroups on one
-// XCD (as in k_sweep), so the cubes that share lines meet in its L2, and the
-// triple's three runs are read and written once from HBM.  Groups with a repeated location and
-// cube cells past N are masked off.
-template <typename T>
-__global__ __launch_bounds__(256) void k_sweep_cube(T* __restrict__ Dd, const T* __restrict__ CC,
-                                                    T* __restrict__ B, const int* __restrict__ tri,
-                                                    const Inst* __restrict__ inst,
-                                                    const long long* __restrict__ preWG, int K, long long totalB)
-{
-    const long long gx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gx < totalB) B[gx] = (T)0;
-    const Inst I = inst[find_seg(preWG, K, (long long)blockIdx.x)];
-    const int lbk = (int)((long long)blockIdx.x - I.wg0);
-    const int xcd = lbk & 7;
-    const int local = lbk >> 3;
-    const int t = (local / I.wpt) * 8 + xcd;
-    if (t >= I.ntri) return;
-    const int N = I.N, n1 = N - 1, n2 = N - 2;
-    const int nt = (N + 3) >> 2;                       // cube tiles per axis
-    // the wave's cube and triple are wave-uniform: keep them scalar
-    const int cube = __builtin_amdgcn_readfirstlane((local % I.wpt) * 4 + (int)(threadIdx.x >> 6));
-    if (cube >= nt * nt * nt) return;
-    const int lane = threadIdx.x & 63;
-    const int tq = cube % nt, tn = (cube / nt) % nt, tj = cube / (nt * nt);
-    const int j = tj * 4 + (lane >> 4), n = tn * 4 + ((lane >> 2) & 3), q = tq * 4 + (lane & 3);
-    if (j >= N || n >= N || q >= N || j == n || j == q || n == q) return;
-    const int* tr = tri + I.tri0 + 3 * t;
-    const int i = tr[0], k = tr[1], p = tr[2];
-    T* __restrict__ Dk = Dd + I.offD;
-    const T* __restrict__ CCk = CC + I.offC;
+// each in the triple's own run of the pair-major layout, so each member's 64
+// lanes fall on 16 runs of 4 consecutive entries.  Groups with a repeated
+// location and cube cells past N are masked off.  STAGE = false (tables too
+// large for LDS, N > 58 in FP64) reads the spread shares from global memory.
+constexpr int kSweepParts = 8;
 
-    // Block numbers of the six members (beta_of with i < k < p worked out):
-    // beta(a, la, b, lb) = a N (N-1)^2 + la (N-1)^2 + b' (N-1) + lb'.
-    const int sq = n1 * n1;
-    const int jn = n - (n > j), jq = q - (q > j), nj = j - (j > n), nq = q - (q > n), qj = j - (j > q),
-              qn = n - (n > q);
-    const int64_t b0 = (int64_t)(i * N) * sq + j * sq + (k - 1) * n1 + jn;
-    const int64_t b1 = (int64_t)(i * N) * sq + j * sq + (p - 1) * n1 + jq;
-    const int64_t b2 = (int64_t)(k * N) * sq + n * sq + i * n1 + nj;
-    const int64_t b3 = (int64_t)(k * N) * sq + n * sq + (p - 1) * n1 + nq;
-    const int64_t b4 = (int64_t)(p * N) * sq + q * sq + i * n1 + qj;
-    const int64_t b5 = (int64_t)(p * N) * sq + q * sq + k * n1 + qn;
-    // The three stored entries (pair_row worked out): each role's run of
-    // the triple starts at a wave-uniform offset; within it, row L(la, lb)
-    // and the compact column.
-    const long long NL = (long long)N * n1;
-    const long long rA = (pair_index(N, i, k) * n2 + (p - 2)) * NL * n2;
-    const long long rB = (pair_index(N, i, p) * n2 + (k - 1)) * NL * n2;
-    const long long rC = (pair_index(N, k, p) * n2 + i) * NL * n2;
-    const int64_t aA = rA + ((j * n1 + jn) * n2 + (jq - (q > n)));
-    const int64_t aB = rB + ((j * n1 + jq) * n2 + (jn - (n > q)));
-    const int64_t aC = rC + ((n * n1 + nq) * n2 + (nj - (j > q)));
-    const T A0 = Dk[aA], B0 = Dk[aB], C0 = Dk[aC];
-    T mean;
+template <typename T>
+__device__ __forceinline__ T six_way_mean(T A0, T B0, T C0, T x0, T x1, T x2, T x3, T x4, T x5)
+{
     if constexpr (sizeof(T) == 8) {
-        const T m0 = A0 + CCk[b0];
-        const T m1 = B0 + CCk[b1];
-        const T m2 = A0 + CCk[b2];
-        const T m3 = C0 + CCk[b3];
-        const T m4 = B0 + CCk[b4];
-        const T m5 = C0 + CCk[b5];
+        const T m0 = A0 + x0;
+        const T m1 = B0 + x1;
+        const T m2 = A0 + x2;
+        const T m3 = C0 + x3;
+        const T m4 = B0 + x4;
+        const T m5 = C0 + x5;
         T sum = m0;
         sum += m1;
         sum += m2;
         sum += m3;
         sum += m4;
         sum += m5;
-        mean = sum / (T)6;
+        return sum / (T)6;
     } else {
-        double sum = add_down((double)A0, (double)CCk[b0]);
+        double sum = add_down((double)A0, (double)x0);
         sum = add_down(sum, (double)B0);
-        sum = add_down(sum, (double)CCk[b1]);
+        sum = add_down(sum, (double)x1);
         sum = add_down(sum, (double)A0);
-        sum = add_down(sum, (double)CCk[b2]);
+        sum = add_down(sum, (double)x2);
         sum = add_down(sum, (double)C0);
-        sum = add_down(sum, (double)CCk[b3]);
+        sum = add_down(sum, (double)x3);
         sum = add_down(sum, (double)B0);
-        sum = add_down(sum, (double)CCk[b4]);
+        sum = add_down(sum, (double)x4);
         sum = add_down(sum, (double)C0);
-        sum = add_down(sum, (double)CCk[b5]);
-        mean = to_float_down(div_down(sum, 6.0));
+        sum = add_down(sum, (double)x5);
+        return to_float_down(div_down(sum, 6.0));
     }
-    Dk[aA] = mean;
-    Dk[aB] = mean;
-    Dk[aC] = mean;
+}
+
+template <typename T, bool STAGE>
+__global__ __launch_bounds__(256) void k_sweep_cube(T* __restrict__ Dd, const T* __restrict__ CC,
+                                                    T* __restrict__ B, const int* __restrict__ tri,
+                                                    const Inst* __restrict__ inst,
+                                                    const long long* __restrict__ preWG, int K, long long totalB,
+                                                    int Nmax)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* __restrict__ X = reinterpret_cast<T*>(smem);   // [6][Nmax][Nmax]
+    const long long gx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gx < totalB) B[gx] = (T)0;
+    const Inst I = inst[find_seg(preWG, K, (long long)blockIdx.x)];
+    const int lbk = (int)((long long)blockIdx.x - I.wg0);
+    const int xcd = lbk & 7;
+    const int local = lbk >> 3;
+    const int t = (local / kSweepParts) * 8 + xcd;
+    if (t >= I.ntri) return;   // whole workgroup
+    const int part = local % kSweepParts;
+    const int N = I.N, n1 = N - 1, n2 = N - 2;
+    const int* tr = tri + I.tri0 + 3 * t;
+    const int i = tr[0], k = tr[1], p = tr[2];
+    T* __restrict__ Dk = Dd + I.offD;
+    const T* __restrict__ CCk = CC + I.offC;
+
+    // Spread shares of the triple: X[m][a][b] = CC of block (f1_m, a, f2_m, b),
+    // (f1, f2) = (i,k), (i,p), (k,i), (k,p), (p,i), (p,k).
+    const int NN = Nmax * Nmax;
+    if constexpr (STAGE) {
+        for (int x = threadIdx.x; x < 6 * N * N; x += 256) {
+            const int m = x / (N * N), r = x - m * N * N;
+            const int a = r / N, b = r - a * N;
+            if (a == b) continue;
+            const int f1 = m < 2 ? i : m < 4 ? k : p;
+            const int f2 = (m == 0 || m == 5) ? k : (m == 1 || m == 3) ? p : i;
+            X[m * NN + a * Nmax + b] = CCk[beta_of(N, f1, a, f2, b)];
+        }
+        __syncthreads();
+    }
+    auto share = [&](int m, int a, int b) -> T {
+        if constexpr (STAGE) {
+            return X[m * NN + a * Nmax + b];
+        } else {
+            const int f1 = m < 2 ? i : m < 4 ? k : p;
+            const int f2 = (m == 0 || m == 5) ? k : (m == 1 || m == 3) ? p : i;
+            return CCk[beta_of(N, f1, a, f2, b)];
+        }
+    };
+
+    const long long NL = (long long)N * n1;
+    const long long rA = (pair_index(N, i, k) * n2 + (p - 2)) * NL * n2;
+    const long long rB = (pair_index(N, i, p) * n2 + (k - 1)) * NL * n2;
+    const long long rC = (pair_index(N, k, p) * n2 + i) * NL * n2;
+    const int nt = (N + 3) >> 2;   // cube tiles per axis
+    const int ncube = nt * nt * nt;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int stride = kSweepParts * 4;
+    for (int c0 = part * 4 + wave; c0 < ncube; c0 += 2 * stride) {
+        int j[2], n[2], q[2];
+        bool ok[2];
+        int64_t aA[2], aB[2], aC[2];
+        T A0[2], B0[2], C0[2];
+        for (int u = 0; u < 2; ++u) {
+            const int cube = c0 + u * stride;
+            const int tq = cube % nt, tn = (cube / nt) % nt, tj = cube / (nt * nt);
+            j[u] = tj * 4 + (lane >> 4);
+            n[u] = tn * 4 + ((lane >> 2) & 3);
+            q[u] = tq * 4 + (lane & 3);
+            ok[u] = cube < ncube && j[u] < N && n[u] < N && q[u] < N && j[u] != n[u] && j[u] != q[u] &&
+                    n[u] != q[u];
+            const int jj = j[u], nn = n[u], qq = q[u];
+            const int jn = nn - (nn > jj), jq = qq - (qq > jj), nj = jj - (jj > nn), nq = qq - (qq > nn);
+            aA[u] = rA + ((jj * n1 + jn) * n2 + (jq - (qq > nn)));
+            aB[u] = rB + ((jj * n1 + jq) * n2 + (jn - (nn > qq)));
+            aC[u] = rC + ((nn * n1 + nq) * n2 + (nj - (jj > qq)));
+            if (ok[u]) {
+                A0[u] = Dk[aA[u]];
+                B0[u] = Dk[aB[u]];
+                C0[u] = Dk[aC[u]];
+            }
+        }
+        for (int u = 0; u < 2; ++u) {
+            if (!ok[u]) continue;
+            const int jj = j[u], nn = n[u], qq = q[u];
+            const T mean = six_way_mean<T>(A0[u], B0[u], C0[u], share(0, jj, nn), share(1, jj, qq), share(2, nn, jj),
+                                           share(3, nn, qq), share(4, qq, jj), share(5, qq, nn));
+            Dk[aA[u]] = mean;
+            Dk[aB[u]] = mean;
+            Dk[aC[u]] = mean;
+        }
+    }
 }
 
 // Step 5: the complementary pair c_ijkn, c_knij (equation (10)) both become
