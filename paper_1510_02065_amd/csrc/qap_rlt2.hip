@@ -79,6 +79,7 @@ struct qap_rlt2 {
     long long pending = 0;   // iterations of qap_rlt2_step whose trace entries are still on the device
     int dmode = qap::kHalfStore;   // D storage and enumeration (kAllBlocks or kHalfStore)
     int Nmax = 0;                  // largest instance
+    int sweep_kind = 0;            // steps 1-3: 0 k_sweep, 1 k_sweep_cube, 2 k_sweep_triple
     bool tuned = false;
     size_t lds_limit = 65536;   // dynamic LDS a workgroup may request
     std::string tune_cache;
@@ -463,6 +464,12 @@ hipError_t enqueue_step(qap_rlt2* h, int step)
                                h->dTri, h->dInst, h->dPreWG, h->K, h->totalB);
             return hipGetLastError();
         }
+        if (h->sweep_kind == 2) {
+            hipLaunchKernelGGL((qap::k_sweep_triple<T>), dim3((unsigned)h->totalWG), dim3(qap::kTripleThreads),
+                               qap::sweep_triple_lds<T>(h->Nmax), st, D, CC, B, h->dTri, h->dInst, h->dPreWG, h->K,
+                               h->totalB);
+            return hipGetLastError();
+        }
         const size_t lds = (size_t)6 * h->Nmax * h->Nmax * sizeof(T);
         if (lds <= h->lds_limit)
             hipLaunchKernelGGL((qap::k_sweep_cube<T, true>), dim3((unsigned)h->totalWG), dim3(256), lds, st, D, CC,
@@ -689,9 +696,24 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
         h->own_stream = true;
     }
 
-    // Packed layout of all instances.
+    // LDS a workgroup may request.
+    {
+        int lim = 0;
+        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && lim > 0)
+            h->lds_limit = (size_t)lim;
+    }
+    // Packed layout of all instances, and the steps 1-3 kernel: one
+    // workgroup per facility triple when the largest instance's triple fits
+    // in LDS, else location cubes; k_sweep when every block is stored.
     const long long align_elems = 128 / (long long)h->elem;
     for (int k = 0; k < count; ++k) h->Nmax = std::max(h->Nmax, (int)Ns[k]);
+    if (h->dmode == qap::kAllBlocks)
+        h->sweep_kind = 0;
+    else {
+        const size_t need = h->precision == QAP_FP64 ? qap::sweep_triple_lds<double>(h->Nmax)
+                                                     : qap::sweep_triple_lds<float>(h->Nmax);
+        h->sweep_kind = need <= h->lds_limit ? 2 : 1;
+    }
     std::vector<int> tri;
     h->inst.resize(count);
     for (int k = 0; k < count; ++k) {
@@ -701,7 +723,7 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
         I.ntri = N * (N - 1) * (N - 2) / 6;
         // sweep workgroups per facility triple: kSweepParts (one stored block
         // per pair), or one per 256 groups (every block)
-        I.wpt = h->dmode != qap::kAllBlocks ? qap::kSweepParts : (N * n1 * n2 + 255) / 256;
+        I.wpt = h->sweep_kind == 0 ? (N * n1 * n2 + 255) / 256 : h->sweep_kind == 1 ? qap::kSweepParts : 1;
         I.pad_ = 0;
         I.offB = h->totalB;
         I.offC = h->totalC;
@@ -726,7 +748,7 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
             h->totalD += nC * I.ldD;
         else   // pair-major, one block per pair, unpadded; instances start 128-byte aligned
             h->totalD += ((nC / 2) * n2 * n2 + align_elems - 1) / align_elems * align_elems;
-        h->totalWG += 8LL * ((I.ntri + 7) / 8) * I.wpt;
+        h->totalWG += h->sweep_kind == 2 ? (long long)I.ntri : 8LL * ((I.ntri + 7) / 8) * I.wpt;
     }
     // Segment-size classes of the three families.
     for (int f = 0; f < 3; ++f) {
@@ -747,11 +769,6 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
 
     // LDS a workgroup may request, and the default configuration of every
     // class: the most problems per wave that fit (families D and C).
-    {
-        int lim = 0;
-        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && lim > 0)
-            h->lds_limit = (size_t)lim;
-    }
     // The B family (one problem per instance) is latency-bound: one column per
     // lane, the smallest segment that holds the problem.
     for (ClassHost& c : h->fam[2]) {

@@ -496,6 +496,105 @@ __global__ __launch_bounds__(256) void k_sweep_cube(T* __restrict__ Dd, const T*
     }
 }
 
+// Steps 1-3 with one workgroup per facility triple i < k < p, everything
+// through LDS (for N small enough that the triple's C run, its spread-share
+// tables and two location tiles of A and B fit; see sweep_triple_lds).  The
+// triple's three stored runs (pair-major layout) are
+//   A[L(j,n)][q'] = D_{(i,j),(k,n)}[p][q],  B[L(j,q)][n'] = D_{(i,j),(p,q)}[k][n],
+//   C[L(n,q)][j'] = D_{(k,n),(p,q)}[i][j],
+// L(a,b) = a (N-1) + b - [b > a], each N (N-1) (N-2) entries.  The workgroup
+// reads the C run whole, then for each tile of JT locations j reads the
+// A and B rows of those j (one contiguous stretch each), forms the means of
+// the tile's groups (j, n, q) as k_sweep_cube does, and writes the rows
+// back; finally it writes the C run back.  Every HBM access is a run of
+// consecutive entries.
+constexpr int kTripleThreads = 1024;
+constexpr int kTripleJT = 2;
+
+template <typename T>
+__host__ __device__ inline size_t sweep_triple_lds(int N)
+{
+    const size_t run = (size_t)N * (N - 1) * (N - 2);
+    return (run + (size_t)6 * N * N + (size_t)2 * kTripleJT * (N - 1) * (N - 2)) * sizeof(T);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__ Dd, const T* __restrict__ CC,
+                                                                 T* __restrict__ B, const int* __restrict__ tri,
+                                                                 const Inst* __restrict__ inst,
+                                                                 const long long* __restrict__ preWG, int K,
+                                                                 long long totalB)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const long long gx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gx < totalB) B[gx] = (T)0;
+    const Inst I = inst[find_seg(preWG, K, (long long)blockIdx.x)];
+    const int t = (int)((long long)blockIdx.x - I.wg0);
+    if (t >= I.ntri) return;   // whole workgroup
+    const int N = I.N, n1 = N - 1, n2 = N - 2;
+    const int run = N * n1 * n2, rowlen = n1 * n2;   // one location j: N-1 rows of N-2
+    T* __restrict__ Cs = reinterpret_cast<T*>(smem);
+    T* __restrict__ X = Cs + run;                    // [6][N][N]
+    T* __restrict__ As = X + 6 * N * N;              // [kTripleJT][rowlen]
+    T* __restrict__ Bs = As + kTripleJT * rowlen;
+    const int* tr = tri + I.tri0 + 3 * t;
+    const int i = tr[0], k = tr[1], p = tr[2];
+    T* __restrict__ Dk = Dd + I.offD;
+    const T* __restrict__ CCk = CC + I.offC;
+    const long long NL = (long long)N * n1;
+    T* __restrict__ gA = Dk + (pair_index(N, i, k) * n2 + (p - 2)) * NL * n2;
+    T* __restrict__ gB = Dk + (pair_index(N, i, p) * n2 + (k - 1)) * NL * n2;
+    T* __restrict__ gC = Dk + (pair_index(N, k, p) * n2 + i) * NL * n2;
+    const int tid = threadIdx.x;
+
+    for (int x = tid; x < run; x += kTripleThreads) Cs[x] = gC[x];
+    for (int x = tid; x < 6 * N * N; x += kTripleThreads) {
+        const int m = x / (N * N), r = x - m * N * N;
+        const int a = r / N, b = r - a * N;
+        if (a == b) continue;
+        const int f1 = m < 2 ? i : m < 4 ? k : p;
+        const int f2 = (m == 0 || m == 5) ? k : (m == 1 || m == 3) ? p : i;
+        X[x] = CCk[beta_of(N, f1, a, f2, b)];
+    }
+
+    for (int j0 = 0; j0 < N; j0 += kTripleJT) {
+        const int jt = min(kTripleJT, N - j0);
+        const int len = jt * rowlen;
+        __syncthreads();   // previous tile written back (and C, X loaded)
+        for (int x = tid; x < len; x += kTripleThreads) {
+            As[x] = gA[(long long)j0 * rowlen + x];
+            Bs[x] = gB[(long long)j0 * rowlen + x];
+        }
+        __syncthreads();
+        for (int g = tid; g < len; g += kTripleThreads) {
+            const int jl = g / rowlen, r = g - jl * rowlen;
+            const int j = j0 + jl;
+            const int nc = r / n2, qc = r - nc * n2;   // n' (skipping j), q'' (skipping j and n)
+            const int n = nc + (nc >= j);
+            const int lo = min(j, n), hi = max(j, n);
+            int q = qc + (qc >= lo);
+            q += (q >= hi);
+            const int jq = q - (q > j);
+            T& a = As[jl * rowlen + r];
+            T& b = Bs[jl * rowlen + jq * n2 + (n - (n > j) - (n > q))];
+            T& c = Cs[(n * n1 + q - (q > n)) * n2 + (j - (j > n) - (j > q))];
+            const T mean = six_way_mean<T>(a, b, c, X[0 * N * N + j * N + n], X[1 * N * N + j * N + q],
+                                           X[2 * N * N + n * N + j], X[3 * N * N + n * N + q],
+                                           X[4 * N * N + q * N + j], X[5 * N * N + q * N + n]);
+            a = mean;
+            b = mean;
+            c = mean;
+        }
+        __syncthreads();
+        for (int x = tid; x < len; x += kTripleThreads) {
+            gA[(long long)j0 * rowlen + x] = As[x];
+            gB[(long long)j0 * rowlen + x] = Bs[x];
+        }
+    }
+    __syncthreads();
+    for (int x = tid; x < run; x += kTripleThreads) gC[x] = Cs[x];
+}
+
 // Step 5: the complementary pair c_ijkn, c_knij (equation (10)) both become
 // their mean.  One thread per C entry; the thread with i < k does the pair.
 template <typename T>
