@@ -123,18 +123,22 @@ __device__ __forceinline__ T tree_sum64(const T (&x)[K], Add add)
     return y[0];
 }
 
-// Per-segment LDS working set:
-// [matrix n*n of T | p: W ints | aux: W ints | way: W ints | pad |
-//  u: W doubles | va: W doubles | vb: W doubles], W = SEG*K.
+// Per-segment LDS working set (W = SEG*K slots):
+// [matrix n*n of T | aux: W ints | p: W shorts | way: W shorts | pad |
+//  u: W doubles | vb: W doubles].  The LDS a wave needs bounds how many
+// waves a CU holds, and the assignment kernels run faster the more it holds,
+// so the row and path indices (< 64 * 64) are 16-bit and no array is kept
+// that another one can stand in for.
 template <typename T, int SEG, int K>
 struct SlotLds {
     static constexpr int W = SEG * K;
     __host__ __device__ static size_t mat_bytes(int n) {
         return (((size_t)n * n * sizeof(T)) + 15) & ~(size_t)15;
     }
-    __host__ __device__ static size_t vec_bytes() {
-        return ((3 * W * sizeof(int) + 15) & ~(size_t)15) + 3 * W * sizeof(double);
+    __host__ __device__ static size_t idx_bytes() {
+        return ((W * sizeof(int) + 2 * W * sizeof(short)) + 15) & ~(size_t)15;
     }
+    __host__ __device__ static size_t vec_bytes() { return idx_bytes() + 2 * W * sizeof(double); }
     __host__ __device__ static size_t bytes(int n) { return mat_bytes(n) + vec_bytes(); }
 };
 
@@ -142,21 +146,19 @@ template <typename T, int SEG, int K>
 struct SlotScratch {
     static constexpr int W = SEG * K;
     T* M;
-    int* p;      // row matched to column c (or -1)
     int* aux;    // row ownership, then sigma (column of row r)
-    int* way;    // predecessor column on the shortest path
-    double* u;   // dual of the row matched to column c
-    double* va;
-    double* vb;
+    short* p;    // row matched to column c (or -1); the flat solver keeps r*n
+    short* way;  // predecessor column on the shortest path
+    double* u;   // dual of the row matched to column c; scratch in the completion
+    double* vb;  // column duals in the canonical passes; scratch in the completion
     __device__ SlotScratch(unsigned char* base, int n) {
         const size_t mb = SlotLds<T, SEG, K>::mat_bytes(n);
         M = reinterpret_cast<T*>(base);
-        p = reinterpret_cast<int*>(base + mb);
-        aux = p + W;
-        way = aux + W;
-        u = reinterpret_cast<double*>(base + mb + ((3 * W * sizeof(int) + 15) & ~(size_t)15));
-        va = u + W;
-        vb = va + W;
+        aux = reinterpret_cast<int*>(base + mb);
+        p = reinterpret_cast<short*>(aux + W);
+        way = p + W;
+        u = reinterpret_cast<double*>(base + mb + SlotLds<T, SEG, K>::idx_bytes());
+        vb = u + W;
     }
 };
 
@@ -299,7 +301,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
     if constexpr (sizeof(T) == 8) {
         // ---- FP64: residual = mean of the residuals under the two points ----
         for (int s = 0; s < K; ++s) {
-            sc.va[c[s]] = vc[s];
+            sc.u[c[s]] = vc[s];
             sc.vb[c[s]] = ur[s];
         }
         wave_sync();
@@ -308,12 +310,12 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             uc[s] = INF;
             vr[s] = INF;
             if (ok[s]) {
-                for (int q = 0; q < n; ++q) uc[s] = tmin(uc[s], M[c[s] * n + q] - (T)sc.va[q]);
+                for (int q = 0; q < n; ++q) uc[s] = tmin(uc[s], M[c[s] * n + q] - (T)sc.u[q]);
                 for (int r = 0; r < n; ++r) vr[s] = tmin(vr[s], M[r * n + c[s]] - (T)sc.vb[r]);
             }
         }
         wave_sync();
-        for (int s = 0; s < K; ++s) sc.va[c[s]] = uc[s];
+        for (int s = 0; s < K; ++s) sc.u[c[s]] = uc[s];
         wave_sync();
         if (R != nullptr) {
             for (int s = 0; s < K; ++s) {
@@ -321,7 +323,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
                 T* Rr = R + c[s];
                 for (int r = 0; r < n; ++r, Rr += ldr) {
                     const T m = M[r * n + c[s]];
-                    const T r1 = (m - vc[s]) - (T)sc.va[r];
+                    const T r1 = (m - vc[s]) - (T)sc.u[r];
                     const T r2 = (m - (T)sc.vb[r]) - vr[s];
                     *Rr = (T)0.5 * (r1 + r2);
                 }
@@ -356,7 +358,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
         // value as the mean of the two residuals) is then >= 0, and each entry
         // and S = sum U + sum V are rounded down once.
         for (int s = 0; s < K; ++s) {
-            sc.va[c[s]] = (double)vc[s];
+            sc.u[c[s]] = (double)vc[s];
             sc.vb[c[s]] = (double)ur[s];
         }
         wave_sync();
@@ -366,7 +368,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             vr[s] = __builtin_huge_val();
             if (ok[s]) {
                 for (int q = 0; q < n; ++q)
-                    uc[s] = __builtin_fmin(uc[s], sub_down((double)M[c[s] * n + q], sc.va[q]));
+                    uc[s] = __builtin_fmin(uc[s], sub_down((double)M[c[s] * n + q], sc.u[q]));
                 for (int r = 0; r < n; ++r)
                     vr[s] = __builtin_fmin(vr[s], sub_down((double)M[r * n + c[s]], sc.vb[r]));
             }
@@ -374,14 +376,14 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             V[s] = ok[s] ? 0.5 * add_down((double)vc[s], vr[s]) : 0.0;   // lane as columns
         }
         wave_sync();
-        for (int s = 0; s < K; ++s) sc.va[c[s]] = U[s];
+        for (int s = 0; s < K; ++s) sc.u[c[s]] = U[s];
         wave_sync();
         if (R != nullptr) {
             for (int s = 0; s < K; ++s) {
                 if (!ok[s]) continue;
                 T* Rr = R + c[s];
                 for (int r = 0; r < n; ++r, Rr += ldr)
-                    *Rr = to_float_down(sub_down(sub_down((double)M[r * n + c[s]], V[s]), sc.va[r]));
+                    *Rr = to_float_down(sub_down(sub_down((double)M[r * n + c[s]], V[s]), sc.u[r]));
             }
         }
         for (int s = 0; s < K; ++s) {
@@ -576,12 +578,14 @@ struct SegBits {
 // column per lane (n <= SEG, SEG >= 16): the first SEG/2 lanes of a segment
 // run the column pass and the other SEG/2 the row pass, each lane holding
 // nodes h and h + SEG/2, so both take n steps together.  A relaxation is
-// written (M - per-step dual) - per-node dual for both passes.  On return
-// (lane as column / as row, K = 1 layout) vc is the column-canonical dual of
-// the lane's column, ur the row-canonical dual of its row and sg its row's
-// column.  Expects sc.p (row of each column) and sc.u (that row's dual).
+// written (M - per-step dual) - per-node dual for both passes.  A fixed
+// node's label is kept aside and its working label set to +inf, so the
+// minimum needs no mask.  On return (lane as column / as row, K = 1 layout)
+// vc is the column-canonical dual of the lane's column, ur the row-canonical
+// dual of its row and sg its row's column.  Expects sc.p (offset r*n of the
+// row matched to each column) and sc.u (that row's dual); poff is this lane's.
 template <typename T, int SEG>
-__device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc, int n, T v, int prow, T& vc,
+__device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc, int n, T v, int poff, T& vc,
                                                 T& ur, int& sg)
 {
     static_assert(SEG >= 16, "two half segments of at least 8 lanes");
@@ -592,14 +596,14 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
     const int l = threadIdx.x & (SEG - 1);
     const T INF = inf_of<T>();
     // sigma (column of each row) and v in LDS.
+    const int prow = poff >= 0 ? poff / n : -1;
     if (l < n && prow >= 0 && prow < n) sc.aux[prow] = l;
     sc.vb[l] = (double)v;
     wave_sync();
     const bool rowpass = l >= H;
     const int h = l & (H - 1);
-    int t[2];
-    T lab[2], w[2];
-    bool done[2];
+    int t[2], base[2];
+    T lab[2], fin[2], w[2];
     for (int q = 0; q < 2; ++q) {
         t[q] = h + q * H;
         const bool okn = t[q] < n;
@@ -612,43 +616,44 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
             w[q] = (T)sc.vb[tc];       // v_q
         }
         lab[q] = okn ? -w[q] : INF;
-        done[q] = !okn;
+        fin[q] = 0;
+        // M entry of node t relaxed through a fixed node with key K (column
+        // pass: K = offset of p(f); row pass: K = sigma(f)) is M[base + K].
+        base[q] = rowpass ? tc * n : tc;
     }
-    // Relaxation of node t through the node f just fixed:
-    //   column pass: M[p(f)][t] - u(f) - v_t;   row pass: M[t][sigma(f)] - v_sigma(f) - u_t.
-    const int sa = rowpass ? n : 1, sb = rowpass ? 1 : n;
     for (int step = 0; step < n; ++step) {
-        T lm = done[0] ? INF : lab[0];
-        if (!done[1] && lab[1] < lm) lm = lab[1];
+        const T lm = tmin(lab[0], lab[1]);
         const T dmin = HS::min(lm);
-        const unsigned long long b0 = HB::get(!done[0] && lab[0] == dmin);
-        const unsigned long long b1 = HB::get(!done[1] && lab[1] == dmin);
+        const bool any = dmin < INF;
+        const unsigned long long b0 = HB::get(any && lab[0] == dmin);
+        const unsigned long long b1 = HB::get(any && lab[1] == dmin);
         const int f = b0 ? HB::first(b0) : (b1 ? HB::first(b1) + H : -1);
         const int fc = f >= 0 ? f : 0;
-        int key = rowpass ? sc.aux[fc] : sc.p[fc];
-        key = (key >= 0 && key < n) ? key : 0;
+        const int key = rowpass ? sc.aux[fc] : (int)sc.p[fc];
         const T s1 = rowpass ? (T)sc.vb[key] : (T)sc.u[fc];
         for (int q = 0; q < 2; ++q) {
-            done[q] = done[q] || (t[q] == f);
-            const int tc = t[q] < n ? t[q] : 0;
-            const T nd = dmin + ((M[tc * sa + key * sb] - s1) - w[q]);
-            if (!done[q] && nd < lab[q]) lab[q] = nd;
+            if (t[q] == f) {
+                fin[q] = lab[q];
+                lab[q] = INF;
+            }
+            const T nd = dmin + ((M[base[q] + key] - s1) - w[q]);
+            if (lab[q] < INF && nd < lab[q]) lab[q] = nd;
         }
     }
     wave_sync();
-    // Column pass: v^c = v + x into va; row pass: u^r = u + y into u (the
-    // solver's row duals are no longer needed).
+    // Column pass: v^c = v + x into vb; row pass: u^r = u + y into u (the
+    // solver's duals are no longer needed).
     for (int q = 0; q < 2; ++q) {
         if (t[q] < n) {
             if (rowpass)
-                sc.u[t[q]] = (double)(w[q] + lab[q]);
+                sc.u[t[q]] = (double)(w[q] + fin[q]);
             else
-                sc.va[t[q]] = (double)(w[q] + lab[q]);
+                sc.vb[t[q]] = (double)(w[q] + fin[q]);
         }
     }
     wave_sync();
     const int lc = l < n ? l : 0;
-    vc = (T)sc.va[lc];
+    vc = (T)sc.vb[lc];
     ur = (T)sc.u[lc];
     sg = sc.aux[lc];
     wave_sync();
@@ -784,19 +789,19 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
         }
     }
 
-    // Row indices for the canonical passes.
-    const int prow = poff >= 0 ? poff / n : -1;
-    sc.p[l] = prow;
-    wave_sync();
     if constexpr (SEG >= 16) {
         T vc, ur;
         int sg;
-        canonical_split<T, SEG>(sc, n, v, prow, vc, ur, sg);
+        canonical_split<T, SEG>(sc, n, v, poff, vc, ur, sg);
         const T vca[1] = {vc};
         const T ura[1] = {ur};
         const int sga[1] = {sg};
         return lap_complete<T, SEG, 1>(sc, n, R, ldr, duals, assign, vca, ura, sga);
     } else {
+        // Row indices for the sequential canonical passes.
+        const int prow = poff >= 0 ? poff / n : -1;
+        sc.p[l] = prow;
+        wave_sync();
         const T va[1] = {v};
         const int pa[1] = {prow};
         const T ua[1] = {ucol};
