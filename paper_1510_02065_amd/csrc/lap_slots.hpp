@@ -123,28 +123,27 @@ __device__ __forceinline__ T tree_sum64(const T (&x)[K], Add add)
     return y[0];
 }
 
-// Per-segment LDS working set (W = SEG*K slots):
-// [matrix n*n of T | aux: W ints | p: W shorts | way: W shorts | pad |
-//  u: W doubles | vb: W doubles].  The LDS a wave needs bounds how many
+// Per-problem LDS working set, for a problem of size n:
+// [matrix n*n of T | aux: n ints | p: n shorts | way: n shorts | pad |
+//  u: n doubles | vb: n doubles].  The LDS a wave needs bounds how many
 // waves a CU holds, and the assignment kernels run faster the more it holds,
-// so the row and path indices (< 64 * 64) are 16-bit and no array is kept
-// that another one can stand in for.
+// so the arrays hold the n columns only (every write is guarded by c < n),
+// row and path indices (< 64 * 64) are 16-bit, and no array is kept that
+// another one can stand in for.
 template <typename T, int SEG, int K>
 struct SlotLds {
-    static constexpr int W = SEG * K;
     __host__ __device__ static size_t mat_bytes(int n) {
         return (((size_t)n * n * sizeof(T)) + 15) & ~(size_t)15;
     }
-    __host__ __device__ static size_t idx_bytes() {
-        return ((W * sizeof(int) + 2 * W * sizeof(short)) + 15) & ~(size_t)15;
+    __host__ __device__ static size_t idx_bytes(int n) {
+        return (((size_t)n * sizeof(int) + 2 * (size_t)n * sizeof(short)) + 15) & ~(size_t)15;
     }
-    __host__ __device__ static size_t vec_bytes() { return idx_bytes() + 2 * W * sizeof(double); }
-    __host__ __device__ static size_t bytes(int n) { return mat_bytes(n) + vec_bytes(); }
+    __host__ __device__ static size_t vec_bytes(int n) { return idx_bytes(n) + 2 * (size_t)n * sizeof(double); }
+    __host__ __device__ static size_t bytes(int n) { return mat_bytes(n) + vec_bytes(n); }
 };
 
 template <typename T, int SEG, int K>
 struct SlotScratch {
-    static constexpr int W = SEG * K;
     T* M;
     int* aux;    // row ownership, then sigma (column of row r)
     short* p;    // row matched to column c (or -1); the flat solver keeps r*n
@@ -155,10 +154,10 @@ struct SlotScratch {
         const size_t mb = SlotLds<T, SEG, K>::mat_bytes(n);
         M = reinterpret_cast<T*>(base);
         aux = reinterpret_cast<int*>(base + mb);
-        p = reinterpret_cast<short*>(aux + W);
-        way = p + W;
-        u = reinterpret_cast<double*>(base + mb + SlotLds<T, SEG, K>::idx_bytes());
-        vb = u + W;
+        p = reinterpret_cast<short*>(aux + n);
+        way = p + n;
+        u = reinterpret_cast<double*>(base + mb + SlotLds<T, SEG, K>::idx_bytes(n));
+        vb = u + n;
     }
 };
 
@@ -227,7 +226,7 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
     wave_sync();
     for (int s = 0; s < K; ++s) {
         if (ok[s] && p[s] >= 0) sc.aux[p[s]] = c[s];
-        sc.vb[c[s]] = (double)v[s];
+        if (ok[s]) sc.vb[c[s]] = (double)v[s];
     }
     wave_sync();
     int sg[K];     // lane as rows: sigma of this lane's rows
@@ -301,6 +300,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
     if constexpr (sizeof(T) == 8) {
         // ---- FP64: residual = mean of the residuals under the two points ----
         for (int s = 0; s < K; ++s) {
+            if (!ok[s]) continue;
             sc.u[c[s]] = vc[s];
             sc.vb[c[s]] = ur[s];
         }
@@ -315,7 +315,8 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             }
         }
         wave_sync();
-        for (int s = 0; s < K; ++s) sc.u[c[s]] = uc[s];
+        for (int s = 0; s < K; ++s)
+            if (ok[s]) sc.u[c[s]] = uc[s];
         wave_sync();
         if (R != nullptr) {
             for (int s = 0; s < K; ++s) {
@@ -358,6 +359,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
         // value as the mean of the two residuals) is then >= 0, and each entry
         // and S = sum U + sum V are rounded down once.
         for (int s = 0; s < K; ++s) {
+            if (!ok[s]) continue;
             sc.u[c[s]] = (double)vc[s];
             sc.vb[c[s]] = (double)ur[s];
         }
@@ -376,7 +378,8 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             V[s] = ok[s] ? 0.5 * add_down((double)vc[s], vr[s]) : 0.0;   // lane as columns
         }
         wave_sync();
-        for (int s = 0; s < K; ++s) sc.u[c[s]] = U[s];
+        for (int s = 0; s < K; ++s)
+            if (ok[s]) sc.u[c[s]] = U[s];
         wave_sync();
         if (R != nullptr) {
             for (int s = 0; s < K; ++s) {
@@ -446,7 +449,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
                 }
             }
         }
-        sc.aux[c[s]] = NONE;
+        if (ok[s]) sc.aux[c[s]] = NONE;
     }
     wave_sync();
     for (int s = 0; s < K; ++s)
@@ -455,6 +458,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
     for (int s = 0; s < K; ++s) {
         p[s] = (ok[s] && sc.aux[crow[s]] == c[s]) ? crow[s] : -1;
         ucol[s] = 0;
+        if (!ok[s]) continue;
         sc.p[c[s]] = p[s];
         sc.u[c[s]] = 0.0;
     }
@@ -514,6 +518,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
                 v[s] -= sh;
                 ucol[s] += sh;
             }
+            if (!ok[s]) continue;
             sc.way[c[s]] = way[s];
             sc.u[c[s]] = (double)ucol[s];
         }
@@ -546,6 +551,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
         for (int s = 0; s < K; ++s) {
             p[s] = newp[s];
             ucol[s] = newu[s];
+            if (!ok[s]) continue;
             sc.p[c[s]] = p[s];
             sc.u[c[s]] = (double)ucol[s];
         }
@@ -598,7 +604,7 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
     // sigma (column of each row) and v in LDS.
     const int prow = poff >= 0 ? poff / n : -1;
     if (l < n && prow >= 0 && prow < n) sc.aux[prow] = l;
-    sc.vb[l] = (double)v;
+    if (l < n) sc.vb[l] = (double)v;
     wave_sync();
     const bool rowpass = l >= H;
     const int h = l & (H - 1);
@@ -695,14 +701,16 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
             }
         }
     }
-    sc.aux[l] = NONE;
+    if (ok) sc.aux[l] = NONE;
     wave_sync();
     if (ok) atomicMin(&sc.aux[crow], l);
     wave_sync();
     int poff = (ok && sc.aux[crow] == l) ? crow * n : -1;   // offset of the matched row
     T ucol = 0;
-    sc.p[l] = poff;
-    sc.u[l] = 0.0;
+    if (ok) {
+        sc.p[l] = poff;
+        sc.u[l] = 0.0;
+    }
     unsigned long long freem = Bits::get(ok && sc.aux[l] == NONE);
     wave_sync();
 
@@ -745,8 +753,10 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
                     v -= sh;
                     ucol += sh;
                 }
-                sc.way[l] = way;
-                sc.u[l] = (double)ucol;
+                if (ok) {
+                    sc.way[l] = way;
+                    sc.u[l] = (double)ucol;
+                }
             }
             wave_sync();
             // Flip the path from the reached column back to the new row: a
@@ -773,8 +783,10 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
             if (aug) {
                 poff = newp;
                 ucol = newu;
-                sc.p[l] = poff;
-                sc.u[l] = (double)ucol;
+                if (ok) {
+                    sc.p[l] = poff;
+                    sc.u[l] = (double)ucol;
+                }
                 row = Bits::first(freem);
                 freem &= freem - 1;
                 dist = INF;
@@ -800,7 +812,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
     } else {
         // Row indices for the sequential canonical passes.
         const int prow = poff >= 0 ? poff / n : -1;
-        sc.p[l] = prow;
+        if (ok) sc.p[l] = prow;
         wave_sync();
         const T va[1] = {v};
         const int pa[1] = {prow};
