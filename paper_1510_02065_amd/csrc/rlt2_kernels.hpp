@@ -511,9 +511,12 @@ __global__ __launch_bounds__(256) void k_sweep_cube(T* __restrict__ Dd, const T*
 constexpr int kTripleThreads = 1024;
 constexpr int kTripleJT = 2;
 
+// LDS bytes of k_sweep_triple at size N; (size_t)-1 when a location tile
+// would exceed the two entries per thread that the kernel prefetches.
 template <typename T>
 __host__ __device__ inline size_t sweep_triple_lds(int N)
 {
+    if ((size_t)kTripleJT * (N - 1) * (N - 2) > 2 * (size_t)kTripleThreads) return (size_t)-1;
     const size_t run = (size_t)N * (N - 1) * (N - 2);
     return (run + (size_t)6 * N * N + (size_t)2 * kTripleJT * (N - 1) * (N - 2)) * sizeof(T);
 }
@@ -557,15 +560,33 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__
         X[x] = CCk[beta_of(N, f1, a, f2, b)];
     }
 
+    // The A and B rows of the next tile are loaded into registers while the
+    // current tile is processed (a tile is at most 2 kTripleThreads entries).
+    T pa[2], pb[2];
+    auto fetch = [&](int j0) {
+        const int len = min(kTripleJT, N - j0) * rowlen;
+        for (int u = 0; u < 2; ++u) {
+            const int x = tid + u * kTripleThreads;
+            if (x < len) {
+                pa[u] = gA[(long long)j0 * rowlen + x];
+                pb[u] = gB[(long long)j0 * rowlen + x];
+            }
+        }
+    };
+    fetch(0);
     for (int j0 = 0; j0 < N; j0 += kTripleJT) {
         const int jt = min(kTripleJT, N - j0);
         const int len = jt * rowlen;
         __syncthreads();   // previous tile written back (and C, X loaded)
-        for (int x = tid; x < len; x += kTripleThreads) {
-            As[x] = gA[(long long)j0 * rowlen + x];
-            Bs[x] = gB[(long long)j0 * rowlen + x];
+        for (int u = 0; u < 2; ++u) {
+            const int x = tid + u * kTripleThreads;
+            if (x < len) {
+                As[x] = pa[u];
+                Bs[x] = pb[u];
+            }
         }
         __syncthreads();
+        if (j0 + kTripleJT < N) fetch(j0 + kTripleJT);
         for (int g = tid; g < len; g += kTripleThreads) {
             const int jl = g / rowlen, r = g - jl * rowlen;
             const int j = j0 + jl;
