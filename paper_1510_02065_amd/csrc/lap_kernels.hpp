@@ -29,6 +29,28 @@ enum : int {
     kHalfStoreTune = 2 // as kHalfStore, parent c_beta only (tuning runs)
 };
 
+// Copy an n x n block (row stride ld in global memory) into LDS (row stride
+// n).  Each lane issues the loads of kStageRows rows before it writes any of
+// them, so a wave waits for HBM once per kStageRows rows instead of once per
+// row; rows past the end re-read row n-1 and are not written.
+constexpr int kStageRows = 16;
+
+template <typename T, int SEG>
+__device__ __forceinline__ void stage_block(T* __restrict__ M, const T* __restrict__ blk, long long ld, int n,
+                                            int lane)
+{
+    for (int r0 = 0; r0 < n; r0 += kStageRows) {
+        for (int c = lane; c < n; c += SEG) {
+            T t[kStageRows];
+#pragma unroll
+            for (int u = 0; u < kStageRows; ++u) t[u] = blk[(long long)min(r0 + u, n - 1) * ld + c];
+#pragma unroll
+            for (int u = 0; u < kStageRows; ++u)
+                if (r0 + u < n) M[(r0 + u) * n + c] = t[u];
+        }
+    }
+}
+
 // D -> C (FAM kFamD: blocks D_beta of size N-2, parent c_beta) or C -> B
 // (kFamC: blocks C_ij of size N-1, parent b_ij), K columns per lane, 64/SEG
 // problems per wave, one wave per workgroup.  parent += S, the block is
@@ -75,11 +97,7 @@ __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __res
         }
     }
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
-    {
-        const T* row = blk;
-        for (int r = 0; r < n; ++r, row += ld)
-            for (int c = lane; c < n; c += SEG) sc.M[r * n + c] = row[c];
-    }
+    stage_block<T, SEG>(sc.M, blk, ld, n, lane);
     wave_sync();
     double S;
     if constexpr (K == 1)
@@ -123,7 +141,7 @@ __global__ __launch_bounds__(64) void k_lap_B_s(T* __restrict__ B, const Inst* _
     const int n = active ? I.N : 0;
     T* blk = B + I.offB;
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
-    for (int e = lane; e < n * n; e += SEG) sc.M[e] = blk[e];
+    stage_block<T, SEG>(sc.M, blk, n, n, lane);
     wave_sync();
     double S;
     if constexpr (K == 1)
@@ -168,7 +186,7 @@ __global__ __launch_bounds__(64) void k_lap_batch(int batch, const int32_t* __re
     const SegScratch<T, SEG> sc(smem + seg * SegLds<T, SEG>::bytes(SEG), SEG);
     T* mat = (b < batch && !bad) ? cost + mat_off[b] : nullptr;
     const int64_t vo = (b < batch && !bad) ? vec_off[b] : 0;
-    for (int e = lane; e < n * n; e += SEG) sc.M[e] = mat[e];
+    stage_block<T, SEG>(sc.M, mat, n, n, lane);
     wave_sync();
     const double S = lap_concentrate_seg<T, SEG>(
         sc, n, (write_residual && n > 0) ? mat : nullptr,
