@@ -11,12 +11,12 @@
 // shared by more columns and more problems than with one column per lane.
 //
 // Solver: the Hungarian method in its shortest-augmenting-path form
-// (Munkres), started from the Jonker-Volgenant column reduction (v_j = column
-// minimum; each row that is the first minimum of some column is matched to the
-// lowest such column).  Each remaining free row is inserted by Dijkstra over
-// columns with absolute tentative distances; the duals of the scanned tree are
-// shifted once when an unmatched column is reached.  Ties are broken towards
-// the lowest column index.
+// (Munkres), started from the two-sided reduction (u_r = row minimum of M,
+// v_c = column minimum of M - u) and a greedy matching on its zero reduced
+// costs (see lap_reduce_start).  Each remaining free row is inserted by
+// Dijkstra over columns with absolute tentative distances; the duals of the
+// scanned tree are shifted once when an unmatched column is reached.  Ties are
+// broken towards the lowest column index.
 //
 // Residual: the optimal dual is not unique, so the residual is taken under a
 // canonical choice that does not depend on the solver's path:
@@ -407,6 +407,66 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
     }
 }
 
+// Start of both solvers.  Row minima u_r of M, then column minima v_c of the
+// reduced rows M_rc - u_r (the two-sided reduction: every reduced cost is
+// >= 0 and each row and column has a zero), then a matching on the zeros:
+// the columns in index order each take the lowest still free row r with
+// M_rc - u_r = v_c.  On the structured blocks of the dual ascent this leaves
+// far fewer rows free than a column reduction alone, and every free row costs
+// Dijkstra steps.  Lane layout as in lap_concentrate_slots (c[s] = this
+// lane's columns, which are also its rows).  On return sc.vb[r] = u_r for every
+// row r < n, kept through the Hungarian phase (a free row enters with that
+// dual); v[s] and row[s] (matched row or -1) for each of the lane's columns;
+// the result is the mask of matched rows (bit r).  sc.u is used as scratch.
+template <typename T, int SEG, int K>
+__device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch<T, SEG, K>& sc, int n,
+                                                               const int (&c)[K], const bool (&ok)[K], T (&v)[K],
+                                                               int (&row)[K])
+{
+    const T* __restrict__ M = sc.M;
+    for (int s = 0; s < K; ++s) {
+        if (!ok[s]) continue;
+        const T* __restrict__ Mr = M + c[s] * n;
+        T um = Mr[0];
+        for (int q = 1; q < n; ++q) {
+            const T m = Mr[q];
+            if (m < um) um = m;
+        }
+        sc.vb[c[s]] = (double)um;
+    }
+    wave_sync();
+    unsigned long long* __restrict__ zeros = reinterpret_cast<unsigned long long*>(sc.u);
+    for (int s = 0; s < K; ++s) {
+        v[s] = 0;
+        row[s] = -1;
+        if (!ok[s]) continue;
+        T vm = M[c[s]] - (T)sc.vb[0];
+        unsigned long long z = 1;
+        for (int r = 1; r < n; ++r) {
+            const T x = M[r * n + c[s]] - (T)sc.vb[r];
+            if (x < vm) {
+                vm = x;
+                z = 1ull << r;
+            } else if (x == vm) {
+                z |= 1ull << r;
+            }
+        }
+        v[s] = vm;
+        zeros[c[s]] = z;
+    }
+    wave_sync();
+    unsigned long long taken = 0;
+    for (int q = 0; q < n; ++q) {
+        const unsigned long long z = zeros[q] & ~taken;
+        const int r = z ? __builtin_ctzll(z) : -1;
+        if (r >= 0) taken |= 1ull << r;
+        for (int s = 0; s < K; ++s)
+            if (c[s] == q) row[s] = r;
+    }
+    wave_sync();
+    return taken;
+}
+
 // Solve, canonicalise and write residuals for the n x n matrix sc.M (in LDS,
 // row stride n, left unchanged).  R (nullable) receives the residual (row
 // stride ldr), duals (nullable) [uc | vc | ur | vr], assign (nullable) the
@@ -431,36 +491,17 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
         ok[s] = c[s] < n;
     }
 
-    // ---- column reduction ---------------------------------------------------
+    // ---- two-sided reduction and greedy start -------------------------------
     T v[K];        // column duals
     int p[K];      // row matched to each column (or -1)
     T ucol[K];     // dual of that row
-    int crow[K];
+    const unsigned long long taken = lap_reduce_start<T, SEG, K>(sc, n, c, ok, v, p);
     for (int s = 0; s < K; ++s) {
-        v[s] = 0;
-        crow[s] = 0;
-        if (ok[s]) {
-            v[s] = M[c[s]];
-            for (int r = 1; r < n; ++r) {
-                const T m = M[r * n + c[s]];
-                if (m < v[s]) {
-                    v[s] = m;
-                    crow[s] = r;
-                }
-            }
-        }
-        if (ok[s]) sc.aux[c[s]] = NONE;
-    }
-    wave_sync();
-    for (int s = 0; s < K; ++s)
-        if (ok[s]) atomicMin(&sc.aux[crow[s]], c[s]);
-    wave_sync();
-    for (int s = 0; s < K; ++s) {
-        p[s] = (ok[s] && sc.aux[crow[s]] == c[s]) ? crow[s] : -1;
-        ucol[s] = 0;
+        ucol[s] = p[s] >= 0 ? (T)sc.vb[p[s]] : (T)0;
         if (!ok[s]) continue;
         sc.p[c[s]] = p[s];
-        sc.u[c[s]] = 0.0;
+        sc.u[c[s]] = (double)ucol[s];
+        sc.aux[c[s]] = ((taken >> c[s]) & 1ull) ? 0 : NONE;   // lane as row c[s]
     }
     wave_sync();
 
@@ -476,7 +517,8 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
             used[s] = false;
         }
         int i0 = i;     // row being scanned
-        T ui0 = 0;      // its dual (a free row has dual 0)
+        const T ufree = (T)sc.vb[i];   // dual of the free row (its row minimum)
+        T ui0 = ufree;  // dual of the row being scanned
         T d0 = 0;       // distance at which row i0 was reached
         int j0 = -1;    // column through which row i0 was reached
         int jend = -1;
@@ -542,7 +584,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
             for (int s = 0; s < K; ++s) {
                 if (c[s] == j) {
                     newp[s] = w >= 0 ? pw : i;
-                    newu[s] = w >= 0 ? uw : dend;
+                    newu[s] = w >= 0 ? uw : ufree + dend;
                 }
             }
             j = w;
@@ -682,36 +724,31 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
 {
     using S = SegS<SEG>;
     using Bits = SegBits<SEG>;
-    constexpr int NONE = 1 << 20;
     const T* __restrict__ M = sc.M;
     const int l = S::lane();
     const bool ok = l < n;
     const T INF = inf_of<T>();
 
-    // ---- column reduction ---------------------------------------------------
-    T v = 0;
-    int crow = 0;
-    if (ok) {
-        v = M[l];
-        for (int r = 1; r < n; ++r) {
-            const T m = M[r * n + l];
-            if (m < v) {
-                v = m;
-                crow = r;
-            }
+    // ---- two-sided reduction and greedy start -------------------------------
+    T v;
+    int poff;   // offset r * n of the matched row, -1 when free
+    T ucol;     // dual of that row
+    unsigned long long freem;   // free rows (bit r)
+    {
+        const int cl[1] = {l};
+        const bool okl[1] = {ok};
+        T va[1];
+        int rw[1];
+        const unsigned long long taken = lap_reduce_start<T, SEG, 1>(sc, n, cl, okl, va, rw);
+        v = va[0];
+        poff = rw[0] >= 0 ? rw[0] * n : -1;
+        ucol = rw[0] >= 0 ? (T)sc.vb[rw[0]] : (T)0;
+        if (ok) {
+            sc.p[l] = poff;
+            sc.u[l] = (double)ucol;
         }
+        freem = ~taken & (n >= 64 ? ~0ull : ((1ull << n) - 1ull));
     }
-    if (ok) sc.aux[l] = NONE;
-    wave_sync();
-    if (ok) atomicMin(&sc.aux[crow], l);
-    wave_sync();
-    int poff = (ok && sc.aux[crow] == l) ? crow * n : -1;   // offset of the matched row
-    T ucol = 0;
-    if (ok) {
-        sc.p[l] = poff;
-        sc.u[l] = 0.0;
-    }
-    unsigned long long freem = Bits::get(ok && sc.aux[l] == NONE);
     wave_sync();
 
     // ---- Hungarian method, all problems of the wave together -----------------
@@ -721,7 +758,8 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
     int way = -1;
     bool used = false;
     int i0n = row >= 0 ? row * n : 0;   // offset of the row being scanned
-    T ui0 = 0;
+    T urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;   // dual of the free row being inserted
+    T ui0 = urow0;                                // dual of the row being scanned
     T d0 = 0;
     int j0 = -1;
     while (ballot64(row >= 0) != 0) {
@@ -776,7 +814,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
                 }
                 if (onpath) {
                     newp = way >= 0 ? pw : row * n;
-                    newu = way >= 0 ? uw : dmin;
+                    newu = way >= 0 ? uw : urow0 + dmin;
                 }
             }
             wave_sync();
@@ -793,7 +831,8 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
                 way = -1;
                 used = false;
                 i0n = row >= 0 ? row * n : 0;
-                ui0 = 0;
+                urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;
+                ui0 = urow0;
                 d0 = 0;
                 j0 = -1;
             }
