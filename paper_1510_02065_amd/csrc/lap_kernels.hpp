@@ -30,23 +30,40 @@ enum : int {
 };
 
 // Copy an n x n block (row stride ld in global memory) into LDS (row stride
-// n).  Each lane issues the loads of kStageRows rows before it writes any of
-// them, so a wave waits for HBM once per kStageRows rows instead of once per
-// row; rows past the end re-read row n-1 and are not written.
-constexpr int kStageRows = 16;
+// n).  Each lane issues the loads of a whole chunk of rows before it writes
+// any of them, so a wave waits for HBM once per chunk instead of once per row:
+// the first kStageRows rows (all of them up to n = 24) in straight-line code,
+// the rest kStageTail at a time.  Rows past the end re-read row n-1 and are
+// not written.  Row offsets are 32-bit (n * ld < 2^31 for n <= 64).
+constexpr int kStageRows = 24;
+constexpr int kStageTail = 8;
 
-template <typename T, int SEG>
+template <typename T, int SEG, int K>
 __device__ __forceinline__ void stage_block(T* __restrict__ M, const T* __restrict__ blk, long long ld, int n,
                                             int lane)
 {
-    for (int r0 = 0; r0 < n; r0 += kStageRows) {
-        for (int c = lane; c < n; c += SEG) {
-            T t[kStageRows];
+    const int ldi = (int)ld;
 #pragma unroll
-            for (int u = 0; u < kStageRows; ++u) t[u] = blk[(long long)min(r0 + u, n - 1) * ld + c];
+    for (int k = 0; k < K; ++k) {
+        const int c = lane + k * SEG;
+        if (c < n) {
+            const T* __restrict__ col = blk + c;
+            {
+                T t[kStageRows];
 #pragma unroll
-            for (int u = 0; u < kStageRows; ++u)
-                if (r0 + u < n) M[(r0 + u) * n + c] = t[u];
+                for (int u = 0; u < kStageRows; ++u) t[u] = col[min(u, n - 1) * ldi];
+#pragma unroll
+                for (int u = 0; u < kStageRows; ++u)
+                    if (u < n) M[u * n + c] = t[u];
+            }
+            for (int r0 = kStageRows; r0 < n; r0 += kStageTail) {
+                T t[kStageTail];
+#pragma unroll
+                for (int u = 0; u < kStageTail; ++u) t[u] = col[min(r0 + u, n - 1) * ldi];
+#pragma unroll
+                for (int u = 0; u < kStageTail; ++u)
+                    if (r0 + u < n) M[(r0 + u) * n + c] = t[u];
+            }
         }
     }
 }
@@ -97,7 +114,7 @@ __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __res
         }
     }
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
-    stage_block<T, SEG>(sc.M, blk, ld, n, lane);
+    stage_block<T, SEG, K>(sc.M, blk, ld, n, lane);
     wave_sync();
     double S;
     if constexpr (K == 1)
@@ -141,7 +158,7 @@ __global__ __launch_bounds__(64) void k_lap_B_s(T* __restrict__ B, const Inst* _
     const int n = active ? I.N : 0;
     T* blk = B + I.offB;
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
-    stage_block<T, SEG>(sc.M, blk, n, n, lane);
+    stage_block<T, SEG, K>(sc.M, blk, n, n, lane);
     wave_sync();
     double S;
     if constexpr (K == 1)
@@ -186,7 +203,7 @@ __global__ __launch_bounds__(64) void k_lap_batch(int batch, const int32_t* __re
     const SegScratch<T, SEG> sc(smem + seg * SegLds<T, SEG>::bytes(SEG), SEG);
     T* mat = (b < batch && !bad) ? cost + mat_off[b] : nullptr;
     const int64_t vo = (b < batch && !bad) ? vec_off[b] : 0;
-    stage_block<T, SEG>(sc.M, mat, n, n, lane);
+    stage_block<T, SEG, 1>(sc.M, mat, n, n, lane);
     wave_sync();
     const double S = lap_concentrate_seg<T, SEG>(
         sc, n, (write_residual && n > 0) ? mat : nullptr,

@@ -423,14 +423,22 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
                                                                const int (&c)[K], const bool (&ok)[K], T (&v)[K],
                                                                int (&row)[K])
 {
+    // Each loop reads kReduceChunk LDS entries before it uses any of them
+    // (indices past n - 1 re-read entry n - 1, which changes no minimum and
+    // sets no new bit), so a lane waits for LDS once per chunk.
+    constexpr int kReduceChunk = 8;
     const T* __restrict__ M = sc.M;
     for (int s = 0; s < K; ++s) {
         if (!ok[s]) continue;
         const T* __restrict__ Mr = M + c[s] * n;
         T um = Mr[0];
-        for (int q = 1; q < n; ++q) {
-            const T m = Mr[q];
-            if (m < um) um = m;
+        for (int q0 = 0; q0 < n; q0 += kReduceChunk) {
+            T m[kReduceChunk];
+#pragma unroll
+            for (int e = 0; e < kReduceChunk; ++e) m[e] = Mr[min(q0 + e, n - 1)];
+#pragma unroll
+            for (int e = 0; e < kReduceChunk; ++e)
+                if (m[e] < um) um = m[e];
         }
         sc.vb[c[s]] = (double)um;
     }
@@ -442,13 +450,22 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
         if (!ok[s]) continue;
         T vm = M[c[s]] - (T)sc.vb[0];
         unsigned long long z = 1;
-        for (int r = 1; r < n; ++r) {
-            const T x = M[r * n + c[s]] - (T)sc.vb[r];
-            if (x < vm) {
-                vm = x;
-                z = 1ull << r;
-            } else if (x == vm) {
-                z |= 1ull << r;
+        for (int r0 = 0; r0 < n; r0 += kReduceChunk) {
+            T x[kReduceChunk];
+#pragma unroll
+            for (int e = 0; e < kReduceChunk; ++e) {
+                const int r = min(r0 + e, n - 1);
+                x[e] = M[r * n + c[s]] - (T)sc.vb[r];
+            }
+#pragma unroll
+            for (int e = 0; e < kReduceChunk; ++e) {
+                const int r = min(r0 + e, n - 1);
+                if (x[e] < vm) {
+                    vm = x[e];
+                    z = 1ull << r;
+                } else if (x[e] == vm) {
+                    z |= 1ull << r;
+                }
             }
         }
         v[s] = vm;
@@ -456,12 +473,20 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
     }
     wave_sync();
     unsigned long long taken = 0;
-    for (int q = 0; q < n; ++q) {
-        const unsigned long long z = zeros[q] & ~taken;
-        const int r = z ? __builtin_ctzll(z) : -1;
-        if (r >= 0) taken |= 1ull << r;
-        for (int s = 0; s < K; ++s)
-            if (c[s] == q) row[s] = r;
+    for (int q0 = 0; q0 < n; q0 += kReduceChunk) {
+        unsigned long long zc[kReduceChunk];
+#pragma unroll
+        for (int e = 0; e < kReduceChunk; ++e) zc[e] = zeros[min(q0 + e, n - 1)];
+#pragma unroll
+        for (int e = 0; e < kReduceChunk; ++e) {
+            const int q = q0 + e;
+            if (q >= n) break;
+            const unsigned long long z = zc[e] & ~taken;
+            const int r = z ? __builtin_ctzll(z) : -1;
+            if (r >= 0) taken |= 1ull << r;
+            for (int s = 0; s < K; ++s)
+                if (c[s] == q) row[s] = r;
+        }
     }
     wave_sync();
     return taken;
