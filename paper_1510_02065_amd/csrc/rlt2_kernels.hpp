@@ -496,6 +496,15 @@ __global__ __launch_bounds__(256) void k_sweep_cube(T* __restrict__ Dd, const T*
     }
 }
 
+// base[idx] with the byte offset computed in 32 bits (idx * sizeof(T) < 2^32),
+// which lets the compiler address through the uniform base pointer plus a
+// 32-bit lane offset instead of keeping a 64-bit address per access.
+template <typename T>
+__device__ __forceinline__ T& at32(T* base, unsigned idx)
+{
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(T));
+}
+
 // Steps 1-3 with one workgroup per facility triple i < k < p, everything
 // through LDS (for N small enough that the triple's C run, its spread-share
 // tables and two location tiles of A and B fit; see sweep_triple_lds).  The
@@ -503,21 +512,37 @@ __global__ __launch_bounds__(256) void k_sweep_cube(T* __restrict__ Dd, const T*
 //   A[L(j,n)][q'] = D_{(i,j),(k,n)}[p][q],  B[L(j,q)][n'] = D_{(i,j),(p,q)}[k][n],
 //   C[L(n,q)][j'] = D_{(k,n),(p,q)}[i][j],
 // L(a,b) = a (N-1) + b - [b > a], each N (N-1) (N-2) entries.  The workgroup
-// reads the C run whole, then for each tile of JT locations j reads the
-// A and B rows of those j (one contiguous stretch each), forms the means of
-// the tile's groups (j, n, q) as k_sweep_cube does, and writes the rows
-// back; finally it writes the C run back.  Every HBM access is a run of
-// consecutive entries.
+// reads the C run whole and the triple's six tables of spread shares, then
+// for each tile of JT locations j reads the A and B rows of those j (one
+// contiguous stretch each), forms the means of the tile's groups (j, n, q) as
+// k_sweep_cube does, and writes the rows back; finally it writes the C run
+// back.  Every HBM access is a run of consecutive entries.
+//
+// Every global load and store is issued unconditionally in straight-line code,
+// with indices past the end clamped to the last entry (a clamped load re-reads
+// it, a clamped store writes back the value it holds), so the compiler knows
+// which loads are still in flight at each LDS write and waits for those alone:
+// the C run, the tables and the first two tiles are all requested before
+// anything is written to LDS, and while a tile is processed the rows of the
+// next two tiles are in flight.
 constexpr int kTripleThreads = 1024;
 constexpr int kTripleJT = 2;
+// Entries of the C run per thread: N (N-1) (N-2) <= kTripleRunRegs * kTripleThreads
+// (N <= 25 in FP64, N <= 32 in FP32), loaded kTripleRunChunk at a time.
+template <typename T>
+constexpr int kTripleRunRegs = sizeof(T) == 8 ? 14 : 30;
+template <typename T>
+constexpr int kTripleRunChunk = sizeof(T) == 8 ? 14 : 10;
 
-// LDS bytes of k_sweep_triple at size N; (size_t)-1 when a location tile
-// would exceed the two entries per thread that the kernel prefetches.
+// LDS bytes of k_sweep_triple at size N; (size_t)-1 when a location tile, the
+// C run or the tables exceed what the kernel holds per thread.
 template <typename T>
 __host__ __device__ inline size_t sweep_triple_lds(int N)
 {
-    if ((size_t)kTripleJT * (N - 1) * (N - 2) > 2 * (size_t)kTripleThreads) return (size_t)-1;
     const size_t run = (size_t)N * (N - 1) * (N - 2);
+    if ((size_t)kTripleJT * (N - 1) * (N - 2) > 2 * (size_t)kTripleThreads) return (size_t)-1;
+    if (run > (size_t)kTripleRunRegs<T> * kTripleThreads) return (size_t)-1;
+    if ((size_t)6 * N * N > 6 * (size_t)kTripleThreads) return (size_t)-1;
     return (run + (size_t)6 * N * N + (size_t)2 * kTripleJT * (N - 1) * (N - 2)) * sizeof(T);
 }
 
@@ -535,10 +560,11 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__
     const int t = (int)((long long)blockIdx.x - I.wg0);
     if (t >= I.ntri) return;   // whole workgroup
     const int N = I.N, n1 = N - 1, n2 = N - 2;
+    const int NN = N * N;
     const int run = N * n1 * n2, rowlen = n1 * n2;   // one location j: N-1 rows of N-2
     T* __restrict__ Cs = reinterpret_cast<T*>(smem);
     T* __restrict__ X = Cs + run;                    // [6][N][N]
-    T* __restrict__ As = X + 6 * N * N;              // [kTripleJT][rowlen]
+    T* __restrict__ As = X + 6 * NN;                 // [kTripleJT][rowlen]
     T* __restrict__ Bs = As + kTripleJT * rowlen;
     const int* tr = tri + I.tri0 + 3 * t;
     const int i = tr[0], k = tr[1], p = tr[2];
@@ -549,44 +575,74 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__
     T* __restrict__ gB = Dk + (pair_index(N, i, p) * n2 + (k - 1)) * NL * n2;
     T* __restrict__ gC = Dk + (pair_index(N, k, p) * n2 + i) * NL * n2;
     const int tid = threadIdx.x;
+    const int ntiles = (N + kTripleJT - 1) / kTripleJT;
 
-    for (int x = tid; x < run; x += kTripleThreads) Cs[x] = gC[x];
-    for (int x = tid; x < 6 * N * N; x += kTripleThreads) {
-        const int m = x / (N * N), r = x - m * N * N;
+    // Requests: the C run, the tables (table m holds the spread shares of the
+    // facility pair (f1, f2) below; diagonal entries are never read and load
+    // CCk[0]), then tiles 0 and 1.
+    constexpr int RR = kTripleRunRegs<T>, RC = kTripleRunChunk<T>;
+    static_assert(RR % RC == 0, "whole chunks");
+    T cr[RC];
+    auto loadC = [&](int c0) {
+#pragma unroll
+        for (int u = 0; u < RC; ++u) cr[u] = at32(gC, (unsigned)min(tid + (c0 + u) * kTripleThreads, run - 1));
+    };
+    auto putC = [&](int c0) {
+#pragma unroll
+        for (int u = 0; u < RC; ++u) Cs[min(tid + (c0 + u) * kTripleThreads, run - 1)] = cr[u];
+    };
+    loadC(0);
+    T xr[6];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+        const int x = min(tid + u * kTripleThreads, 6 * NN - 1);
+        const int m = x / NN, r = x - m * NN;
         const int a = r / N, b = r - a * N;
-        if (a == b) continue;
         const int f1 = m < 2 ? i : m < 4 ? k : p;
         const int f2 = (m == 0 || m == 5) ? k : (m == 1 || m == 3) ? p : i;
-        X[x] = CCk[beta_of(N, f1, a, f2, b)];
+        xr[u] = CCk[a == b ? 0 : beta_of(N, f1, a, f2, b)];
     }
-
-    // The A and B rows of the next tile are loaded into registers while the
-    // current tile is processed (a tile is at most 2 kTripleThreads entries).
-    T pa[2], pb[2];
-    auto fetch = [&](int j0) {
+    auto fetch = [&](T (&ra)[2], T (&rb)[2], int tix) {
+        const int j0 = min(tix, ntiles - 1) * kTripleJT;
         const int len = min(kTripleJT, N - j0) * rowlen;
+        T* __restrict__ tA = gA + (long long)j0 * rowlen;
+        T* __restrict__ tB = gB + (long long)j0 * rowlen;
+#pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int x = tid + u * kTripleThreads;
-            if (x < len) {
-                pa[u] = gA[(long long)j0 * rowlen + x];
-                pb[u] = gB[(long long)j0 * rowlen + x];
-            }
+            const unsigned x = (unsigned)min(tid + u * kTripleThreads, len - 1);
+            ra[u] = at32(tA, x);
+            rb[u] = at32(tB, x);
         }
     };
-    fetch(0);
-    for (int j0 = 0; j0 < N; j0 += kTripleJT) {
-        const int jt = min(kTripleJT, N - j0);
-        const int len = jt * rowlen;
-        __syncthreads();   // previous tile written back (and C, X loaded)
+    T pa0[2], pb0[2], pa1[2], pb1[2];
+    fetch(pa0, pb0, 0);
+    fetch(pa1, pb1, 1);
+    putC(0);
+#pragma unroll
+    for (int u = 0; u < 6; ++u) X[min(tid + u * kTripleThreads, 6 * NN - 1)] = xr[u];
+#pragma unroll
+    for (int c0 = RC; c0 < RR; c0 += RC) {   // FP32 only: the rest of the run
+        loadC(c0);
+        putC(c0);
+    }
+
+    // One tile: its rows from registers into LDS, the rows of the tile two
+    // ahead requested into the same registers, the tile's groups, the rows
+    // back to HBM.
+    auto tile = [&](T (&ra)[2], T (&rb)[2], int tix) {
+        const int j0 = tix * kTripleJT;
+        const int len = min(kTripleJT, N - j0) * rowlen;
+        T* __restrict__ tA = gA + (long long)j0 * rowlen;
+        T* __restrict__ tB = gB + (long long)j0 * rowlen;
+        __syncthreads();   // previous tile written back (C and X in place)
+#pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int x = tid + u * kTripleThreads;
-            if (x < len) {
-                As[x] = pa[u];
-                Bs[x] = pb[u];
-            }
+            const int x = min(tid + u * kTripleThreads, len - 1);
+            As[x] = ra[u];
+            Bs[x] = rb[u];
         }
         __syncthreads();
-        if (j0 + kTripleJT < N) fetch(j0 + kTripleJT);
+        fetch(ra, rb, tix + 2);
         for (int g = tid; g < len; g += kTripleThreads) {
             const int jl = g / rowlen, r = g - jl * rowlen;
             const int j = j0 + jl;
@@ -599,21 +655,37 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__
             T& a = As[jl * rowlen + r];
             T& b = Bs[jl * rowlen + jq * n2 + (n - (n > j) - (n > q))];
             T& c = Cs[(n * n1 + q - (q > n)) * n2 + (j - (j > n) - (j > q))];
-            const T mean = six_way_mean<T>(a, b, c, X[0 * N * N + j * N + n], X[1 * N * N + j * N + q],
-                                           X[2 * N * N + n * N + j], X[3 * N * N + n * N + q],
-                                           X[4 * N * N + q * N + j], X[5 * N * N + q * N + n]);
+            const T mean = six_way_mean<T>(a, b, c, X[0 * NN + j * N + n], X[1 * NN + j * N + q],
+                                           X[2 * NN + n * N + j], X[3 * NN + n * N + q],
+                                           X[4 * NN + q * N + j], X[5 * NN + q * N + n]);
             a = mean;
             b = mean;
             c = mean;
         }
         __syncthreads();
-        for (int x = tid; x < len; x += kTripleThreads) {
-            gA[(long long)j0 * rowlen + x] = As[x];
-            gB[(long long)j0 * rowlen + x] = Bs[x];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const unsigned x = (unsigned)min(tid + u * kTripleThreads, len - 1);
+            at32(tA, x) = As[x];
+            at32(tB, x) = Bs[x];
         }
+    };
+    int tix = 0;
+    for (; tix + 1 < ntiles; tix += 2) {
+        tile(pa0, pb0, tix);
+        tile(pa1, pb1, tix + 1);
     }
+    if (tix < ntiles) tile(pa0, pb0, tix);
     __syncthreads();
-    for (int x = tid; x < run; x += kTripleThreads) gC[x] = Cs[x];
+    // The thread index passes through an empty asm so that these offsets are
+    // computed here rather than kept in registers from the first C loop.
+    int tid2 = tid;
+    asm volatile("" : "+v"(tid2));
+#pragma unroll
+    for (int u = 0; u < RR; ++u) {
+        const unsigned x = (unsigned)min(tid2 + u * kTripleThreads, run - 1);
+        at32(gC, x) = Cs[x];
+    }
 }
 
 // Step 5: the complementary pair c_ijkn, c_knij (equation (10)) both become
