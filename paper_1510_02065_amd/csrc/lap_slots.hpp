@@ -651,20 +651,22 @@ struct SegBits {
 // column per lane (n <= SEG, SEG >= 16): the first SEG/2 lanes of a segment
 // run the column pass and the other SEG/2 the row pass, each lane holding
 // nodes h and h + SEG/2, so both take n steps together.  A relaxation is
-// written (M - per-step dual) - per-node dual for both passes.  A fixed
-// node's label is kept aside and its working label set to +inf, so the
-// minimum needs no mask.  On return (lane as column / as row, K = 1 layout)
-// vc is the column-canonical dual of the lane's column, ur the row-canonical
-// dual of its row and sg its row's column.  Expects sc.p (offset r*n of the
-// row matched to each column) and sc.u (that row's dual); poff is this lane's.
+// written (M - per-step dual) - per-node dual for both passes.  A fixed node
+// keeps its label (it is never relaxed again) and is masked out of the
+// minimum; the lowest node at the minimum is the minimum over the lanes of
+// their lowest candidate index.  On return (lane as column / as row, K = 1
+// layout) vc is the column-canonical dual of the lane's column, ur the
+// row-canonical dual of its row and sg its row's column.  Expects sc.p
+// (offset r*n of the row matched to each column) and sc.u (that row's dual);
+// poff is this lane's.
 template <typename T, int SEG>
 __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc, int n, T v, int poff, T& vc,
                                                 T& ur, int& sg)
 {
     static_assert(SEG >= 16, "two half segments of at least 8 lanes");
     constexpr int H = SEG / 2;
+    constexpr int NONE = 1 << 20;
     using HS = SegS<H>;
-    using HB = SegBits<H>;
     const T* __restrict__ M = sc.M;
     const int l = threadIdx.x & (SEG - 1);
     const T INF = inf_of<T>();
@@ -676,7 +678,8 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
     const bool rowpass = l >= H;
     const int h = l & (H - 1);
     int t[2], base[2];
-    T lab[2], fin[2], w[2];
+    T lab[2], w[2];
+    bool fx[2];   // fixed (or absent) node
     for (int q = 0; q < 2; ++q) {
         t[q] = h + q * H;
         const bool okn = t[q] < n;
@@ -688,29 +691,23 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
         } else {
             w[q] = (T)sc.vb[tc];       // v_q
         }
-        lab[q] = okn ? -w[q] : INF;
-        fin[q] = 0;
+        lab[q] = okn ? -w[q] : (T)0;
+        fx[q] = !okn;
         // M entry of node t relaxed through a fixed node with key K (column
         // pass: K = offset of p(f); row pass: K = sigma(f)) is M[base + K].
         base[q] = rowpass ? tc * n : tc;
     }
     for (int step = 0; step < n; ++step) {
-        const T lm = tmin(lab[0], lab[1]);
-        const T dmin = HS::min(lm);
-        const bool any = dmin < INF;
-        const unsigned long long b0 = HB::get(any && lab[0] == dmin);
-        const unsigned long long b1 = HB::get(any && lab[1] == dmin);
-        const int f = b0 ? HB::first(b0) : (b1 ? HB::first(b1) + H : -1);
-        const int fc = f >= 0 ? f : 0;
+        const T dmin = HS::min(tmin(fx[0] ? INF : lab[0], fx[1] ? INF : lab[1]));
+        const int cand = (!fx[0] && lab[0] == dmin) ? t[0] : ((!fx[1] && lab[1] == dmin) ? t[1] : NONE);
+        const int f = HS::imin(cand);
+        const int fc = f < n ? f : 0;
         const int key = rowpass ? sc.aux[fc] : (int)sc.p[fc];
         const T s1 = rowpass ? (T)sc.vb[key] : (T)sc.u[fc];
         for (int q = 0; q < 2; ++q) {
-            if (t[q] == f) {
-                fin[q] = lab[q];
-                lab[q] = INF;
-            }
+            fx[q] = fx[q] || (t[q] == f);
             const T nd = dmin + ((M[base[q] + key] - s1) - w[q]);
-            if (lab[q] < INF && nd < lab[q]) lab[q] = nd;
+            if (!fx[q] && nd < lab[q]) lab[q] = nd;
         }
     }
     wave_sync();
@@ -719,9 +716,9 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
     for (int q = 0; q < 2; ++q) {
         if (t[q] < n) {
             if (rowpass)
-                sc.u[t[q]] = (double)(w[q] + fin[q]);
+                sc.u[t[q]] = (double)(w[q] + lab[q]);
             else
-                sc.vb[t[q]] = (double)(w[q] + fin[q]);
+                sc.vb[t[q]] = (double)(w[q] + lab[q]);
         }
     }
     wave_sync();
