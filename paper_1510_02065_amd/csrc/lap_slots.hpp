@@ -37,6 +37,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lap_wave.hpp"
 #include "rlt2_kernels.hpp"
 
@@ -425,8 +427,10 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
 {
     // Each loop reads kReduceChunk LDS entries before it uses any of them
     // (indices past n - 1 re-read entry n - 1, which changes no minimum and
-    // sets no new bit), so a lane waits for LDS once per chunk.
+    // sets no new bit), so a lane waits for LDS once per chunk.  Zero masks are
+    // 32-bit when a problem has at most 32 columns.
     constexpr int kReduceChunk = 8;
+    using Mask = std::conditional_t<(SEG * K <= 32), unsigned, unsigned long long>;
     const T* __restrict__ M = sc.M;
     for (int s = 0; s < K; ++s) {
         if (!ok[s]) continue;
@@ -443,13 +447,14 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
         sc.vb[c[s]] = (double)um;
     }
     wave_sync();
-    unsigned long long* __restrict__ zeros = reinterpret_cast<unsigned long long*>(sc.u);
+    Mask zc[K];   // zero mask of each of this lane's columns
     for (int s = 0; s < K; ++s) {
         v[s] = 0;
         row[s] = -1;
+        zc[s] = 0;
         if (!ok[s]) continue;
         T vm = M[c[s]] - (T)sc.vb[0];
-        unsigned long long z = 1;
+        Mask z = 1;
         for (int r0 = 0; r0 < n; r0 += kReduceChunk) {
             T x[kReduceChunk];
 #pragma unroll
@@ -462,34 +467,84 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
                 const int r = min(r0 + e, n - 1);
                 if (x[e] < vm) {
                     vm = x[e];
-                    z = 1ull << r;
+                    z = Mask(1) << r;
                 } else if (x[e] == vm) {
-                    z |= 1ull << r;
+                    z |= Mask(1) << r;
                 }
             }
         }
         v[s] = vm;
-        zeros[c[s]] = z;
+        zc[s] = z;
     }
-    wave_sync();
-    unsigned long long taken = 0;
-    for (int q0 = 0; q0 < n; q0 += kReduceChunk) {
-        unsigned long long zc[kReduceChunk];
+    if constexpr (K == 1) {
+        // One column per lane: the greedy matching runs on the scalar unit,
+        // each segment's column q read from its lane q, and that lane takes
+        // the chosen row.
+        constexpr int LPW = 64 / SEG;
+        const int seg = (threadIdx.x & 63) / SEG;
+        int rowv = -1;
+        Mask tk[LPW];
+        int ns[LPW];
+        int nmax = 0;
 #pragma unroll
-        for (int e = 0; e < kReduceChunk; ++e) zc[e] = zeros[min(q0 + e, n - 1)];
-#pragma unroll
-        for (int e = 0; e < kReduceChunk; ++e) {
-            const int q = q0 + e;
-            if (q >= n) break;
-            const unsigned long long z = zc[e] & ~taken;
-            const int r = z ? __builtin_ctzll(z) : -1;
-            if (r >= 0) taken |= 1ull << r;
-            for (int s = 0; s < K; ++s)
-                if (c[s] == q) row[s] = r;
+        for (int g = 0; g < LPW; ++g) {
+            tk[g] = 0;
+            ns[g] = __builtin_amdgcn_readlane(n, g * SEG);
+            nmax = ::max(nmax, ns[g]);
         }
+        for (int q = 0; q < nmax; ++q) {
+#pragma unroll
+            for (int g = 0; g < LPW; ++g) {
+                if (q >= ns[g]) continue;
+                Mask z;
+                if constexpr (sizeof(Mask) == 4) {
+                    z = (Mask)__builtin_amdgcn_readlane((int)zc[0], g * SEG + q);
+                } else {
+                    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)zc[0], g * SEG + q);
+                    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(zc[0] >> 32), g * SEG + q);
+                    z = ((Mask)hi << 32) | lo;
+                }
+                z &= ~tk[g];
+                if (z) {
+                    const int r = sizeof(Mask) == 4 ? __builtin_ctz((unsigned)z) : __builtin_ctzll((unsigned long long)z);
+                    tk[g] |= Mask(1) << r;
+                    if ((int)(threadIdx.x & 63) == g * SEG + q) rowv = r;
+                }
+            }
+        }
+        row[0] = ok[0] ? rowv : -1;
+        Mask taken = tk[0];
+#pragma unroll
+        for (int g = 1; g < LPW; ++g)
+            if (seg == g) taken = tk[g];
+        wave_sync();
+        return (unsigned long long)taken;
+    } else {
+        Mask* __restrict__ zeros = reinterpret_cast<Mask*>(sc.u);
+        for (int s = 0; s < K; ++s)
+            if (ok[s]) zeros[c[s]] = zc[s];
+        wave_sync();
+        Mask taken = 0;
+        for (int q0 = 0; q0 < n; q0 += kReduceChunk) {
+            Mask zq[kReduceChunk];
+#pragma unroll
+            for (int e = 0; e < kReduceChunk; ++e) zq[e] = zeros[min(q0 + e, n - 1)];
+#pragma unroll
+            for (int e = 0; e < kReduceChunk; ++e) {
+                const int q = q0 + e;
+                if (q >= n) break;
+                const Mask z = zq[e] & ~taken;
+                const int r = z ? (sizeof(Mask) == 4 ? __builtin_ctz((unsigned)z)
+                                                     : __builtin_ctzll((unsigned long long)z))
+                                : -1;
+                if (r >= 0) taken |= Mask(1) << r;
+                for (int s = 0; s < K; ++s)
+                    if (c[s] == q) row[s] = r;
+            }
+        }
+        wave_sync();
+        return (unsigned long long)taken;
     }
-    wave_sync();
-    return taken;
 }
 
 // Solve, canonicalise and write residuals for the n x n matrix sc.M (in LDS,
