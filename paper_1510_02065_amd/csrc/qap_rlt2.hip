@@ -82,6 +82,7 @@ struct qap_rlt2 {
     int sweep_kind = 0;            // steps 1-3: 0 k_sweep, 1 k_sweep_cube, 2 k_sweep_triple
     bool tuned = false;
     size_t lds_limit = 65536;   // dynamic LDS a workgroup may request
+    int num_cu = 256;           // compute units of the device
     std::string tune_cache;
     size_t elem = 8;   // bytes per reduced cost
     std::vector<qap::Inst> inst;
@@ -465,9 +466,19 @@ hipError_t enqueue_step(qap_rlt2* h, int step)
             return hipGetLastError();
         }
         if (h->sweep_kind == 2) {
-            hipLaunchKernelGGL((qap::k_sweep_triple<T>), dim3((unsigned)h->totalWG), dim3(qap::kTripleThreads),
-                               qap::sweep_triple_lds<T>(h->Nmax), st, D, CC, B, h->dTri, h->dInst, h->dPreWG, h->K,
-                               h->totalB);
+            // When a CU holds only one triple's workgroup, one persistent
+            // workgroup per CU walks the triples and overlaps each triple's
+            // start with the previous one's tiles; when it holds two, one
+            // workgroup per triple lets the hardware overlap them.
+            const size_t lds = qap::sweep_triple_lds<T>(h->Nmax);
+            if (h->lds_limit / lds >= 2) {
+                hipLaunchKernelGGL((qap::k_sweep_triple<T>), dim3((unsigned)h->totalWG), dim3(qap::kTripleThreads), lds,
+                                   st, D, CC, B, h->dTri, h->dInst, h->dPreWG, h->K, h->totalB);
+            } else {
+                const long long grid = std::min<long long>(h->totalWG, h->num_cu);
+                hipLaunchKernelGGL((qap::k_sweep_triple_p<T>), dim3((unsigned)grid), dim3(qap::kTripleThreads), lds,
+                                   st, D, CC, B, h->dTri, h->dInst, h->dPreWG, h->K, h->totalB, h->totalWG, h->Nmax);
+            }
             return hipGetLastError();
         }
         const size_t lds = (size_t)6 * h->Nmax * h->Nmax * sizeof(T);
@@ -701,6 +712,8 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
         int lim = 0;
         if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess && lim > 0)
             h->lds_limit = (size_t)lim;
+        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && lim > 0)
+            h->num_cu = lim;
     }
     // Packed layout of all instances, and the steps 1-3 kernel: one
     // workgroup per facility triple when the largest instance's triple fits

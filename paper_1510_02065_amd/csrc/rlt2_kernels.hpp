@@ -688,6 +688,217 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__
     }
 }
 
+// k_sweep_triple as a persistent kernel: each workgroup walks the triples
+// blockIdx.x, blockIdx.x + gridDim.x, ... (all triples of an instance are
+// the same work, so a static walk is balanced).  As soon as a triple's C run
+// and tables are in LDS, the next triple's are requested into the registers
+// they came through, and the two-tiles-ahead prefetch runs on into the next
+// triple's first tiles, so a triple's start overlaps the previous one's tiles.
+// LDS is laid out for the largest instance.  Same arithmetic and order as
+// k_sweep_triple.
+template <typename T>
+struct TripleRef {
+    int N, n1, n2, NN, run, rowlen, ntiles, i, k, p;
+    T* gA;
+    T* gB;
+    T* gC;
+    const T* CCk;
+};
+
+template <typename T>
+__device__ __forceinline__ TripleRef<T> triple_ref(T* Dd, const T* CC, const int* __restrict__ tri,
+                                                   const Inst* __restrict__ inst, const long long* __restrict__ preWG,
+                                                   int K, long long Tg)
+{
+    const Inst I = inst[find_seg(preWG, K, Tg)];
+    const int t = (int)(Tg - I.wg0);
+    TripleRef<T> r;
+    r.N = I.N;
+    r.n1 = r.N - 1;
+    r.n2 = r.N - 2;
+    r.NN = r.N * r.N;
+    r.run = r.N * r.n1 * r.n2;
+    r.rowlen = r.n1 * r.n2;
+    r.ntiles = (r.N + kTripleJT - 1) / kTripleJT;
+    const int* tr = tri + I.tri0 + 3 * t;
+    r.i = tr[0];
+    r.k = tr[1];
+    r.p = tr[2];
+    T* Dk = Dd + I.offD;
+    const long long NL = (long long)r.N * r.n1;
+    r.gA = Dk + (pair_index(r.N, r.i, r.k) * r.n2 + (r.p - 2)) * NL * r.n2;
+    r.gB = Dk + (pair_index(r.N, r.i, r.p) * r.n2 + (r.k - 1)) * NL * r.n2;
+    r.gC = Dk + (pair_index(r.N, r.k, r.p) * r.n2 + r.i) * NL * r.n2;
+    r.CCk = CC + I.offC;
+    return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict__ Dd, const T* __restrict__ CC,
+                                                                   T* __restrict__ B, const int* __restrict__ tri,
+                                                                   const Inst* __restrict__ inst,
+                                                                   const long long* __restrict__ preWG, int K,
+                                                                   long long totalB, long long totalTri, int Nmax)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x;
+    for (long long x = (long long)blockIdx.x * kTripleThreads + tid; x < totalB;
+         x += (long long)gridDim.x * kTripleThreads)
+        B[x] = (T)0;
+    long long Tg = blockIdx.x;
+    if (Tg >= totalTri) return;   // whole workgroup
+    T* __restrict__ Cs = reinterpret_cast<T*>(smem);
+    T* __restrict__ X = Cs + Nmax * (Nmax - 1) * (Nmax - 2);   // [6][N][N]
+    T* __restrict__ As = X + 6 * Nmax * Nmax;                  // [kTripleJT][rowlen]
+    T* __restrict__ Bs = As + kTripleJT * (Nmax - 1) * (Nmax - 2);
+
+    constexpr int RR = kTripleRunRegs<T>, RC = kTripleRunChunk<T>;
+    static_assert(RR % RC == 0, "whole chunks");
+    T cr[RC];
+    T xr[6];
+    // The run and tables of triple r go through cr and xr.
+    auto loadC = [&](T* gC, int run, int c0) {
+#pragma unroll
+        for (int u = 0; u < RC; ++u) cr[u] = at32(gC, (unsigned)min(tid + (c0 + u) * kTripleThreads, run - 1));
+    };
+    auto putC = [&](int run, int c0) {
+#pragma unroll
+        for (int u = 0; u < RC; ++u) Cs[min(tid + (c0 + u) * kTripleThreads, run - 1)] = cr[u];
+    };
+    auto loadX = [&](const T* CCk, int N, int i, int k, int p) {
+        const int NN = N * N;
+#pragma unroll
+        for (int u = 0; u < 6; ++u) {
+            const int x = min(tid + u * kTripleThreads, 6 * NN - 1);
+            const int m = x / NN, rr = x - m * NN;
+            const int a = rr / N, b = rr - a * N;
+            const int f1 = m < 2 ? i : m < 4 ? k : p;
+            const int f2 = (m == 0 || m == 5) ? k : (m == 1 || m == 3) ? p : i;
+            xr[u] = CCk[a == b ? 0 : beta_of(N, f1, a, f2, b)];
+        }
+    };
+    auto putX = [&](int N) {
+#pragma unroll
+        for (int u = 0; u < 6; ++u) X[min(tid + u * kTripleThreads, 6 * N * N - 1)] = xr[u];
+    };
+    // Rows of the tile starting at location j0 of runs (gA, gB).
+    auto fetch = [&](T (&ra)[2], T (&rb)[2], T* gA, T* gB, int N, int rowlen, int j0) {
+        const int len = min(kTripleJT, N - j0) * rowlen;
+        T* tA = gA + (long long)j0 * rowlen;
+        T* tB = gB + (long long)j0 * rowlen;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const unsigned x = (unsigned)min(tid + u * kTripleThreads, len - 1);
+            ra[u] = at32(tA, x);
+            rb[u] = at32(tB, x);
+        }
+    };
+
+    TripleRef<T> cur = triple_ref<T>(Dd, CC, tri, inst, preWG, K, Tg);
+    T pa0[2], pb0[2], pa1[2], pb1[2];
+    loadC(cur.gC, cur.run, 0);
+    loadX(cur.CCk, cur.N, cur.i, cur.k, cur.p);
+    fetch(pa0, pb0, cur.gA, cur.gB, cur.N, cur.rowlen, 0);
+    fetch(pa1, pb1, cur.gA, cur.gB, cur.N, cur.rowlen, min(kTripleJT, (cur.ntiles - 1) * kTripleJT));
+    for (;;) {
+        const int N = cur.N, n1 = cur.n1, n2 = cur.n2, NN = cur.NN, rowlen = cur.rowlen, ntiles = cur.ntiles;
+        const int run = cur.run;
+        T* const gA = cur.gA;
+        T* const gB = cur.gB;
+        T* const gC = cur.gC;
+        putC(run, 0);
+        putX(N);
+#pragma unroll
+        for (int c0 = RC; c0 < RR; c0 += RC) {   // FP32 only: the rest of the run
+            loadC(gC, run, c0);
+            putC(run, c0);
+        }
+        const long long Tn = Tg + gridDim.x;
+        const bool more = Tn < totalTri;
+        const TripleRef<T> nxt = triple_ref<T>(Dd, CC, tri, inst, preWG, K, more ? Tn : Tg);
+        T* const hA = nxt.gA;
+        T* const hB = nxt.gB;
+        const int hN = nxt.N, hrow = nxt.rowlen, hlast = (nxt.ntiles - 1) * kTripleJT;
+        loadC(nxt.gC, nxt.run, 0);   // registers free again: the next triple's run and tables
+        loadX(nxt.CCk, nxt.N, nxt.i, nxt.k, nxt.p);
+        auto tile = [&](T (&ra)[2], T (&rb)[2], int tix) {
+            const int j0 = tix * kTripleJT;
+            const int len = min(kTripleJT, N - j0) * rowlen;
+            T* __restrict__ tA = gA + (long long)j0 * rowlen;
+            T* __restrict__ tB = gB + (long long)j0 * rowlen;
+            __syncthreads();   // previous tile written back (C and X in place)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int x = min(tid + u * kTripleThreads, len - 1);
+                As[x] = ra[u];
+                Bs[x] = rb[u];
+            }
+            __syncthreads();
+            // Two tiles ahead: this triple's, or past its end the next one's.
+            const int t2 = tix + 2;
+            const bool on = t2 < ntiles;
+            fetch(ra, rb, on ? gA : hA, on ? gB : hB, on ? N : hN, on ? rowlen : hrow,
+                  on ? t2 * kTripleJT : min((t2 - ntiles) * kTripleJT, hlast));
+            for (int g = tid; g < len; g += kTripleThreads) {
+                const int jl = g / rowlen, r = g - jl * rowlen;
+                const int j = j0 + jl;
+                const int nc = r / n2, qc = r - nc * n2;   // n' (skipping j), q'' (skipping j and n)
+                const int n = nc + (nc >= j);
+                const int lo = min(j, n), hi = max(j, n);
+                int q = qc + (qc >= lo);
+                q += (q >= hi);
+                const int jq = q - (q > j);
+                T& a = As[jl * rowlen + r];
+                T& b = Bs[jl * rowlen + jq * n2 + (n - (n > j) - (n > q))];
+                T& c = Cs[(n * n1 + q - (q > n)) * n2 + (j - (j > n) - (j > q))];
+                const T mean = six_way_mean<T>(a, b, c, X[0 * NN + j * N + n], X[1 * NN + j * N + q],
+                                               X[2 * NN + n * N + j], X[3 * NN + n * N + q],
+                                               X[4 * NN + q * N + j], X[5 * NN + q * N + n]);
+                a = mean;
+                b = mean;
+                c = mean;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const unsigned x = (unsigned)min(tid + u * kTripleThreads, len - 1);
+                at32(tA, x) = As[x];
+                at32(tB, x) = Bs[x];
+            }
+        };
+        int tix = 0;
+        for (; tix + 1 < ntiles; tix += 2) {
+            tile(pa0, pb0, tix);
+            tile(pa1, pb1, tix + 1);
+        }
+        if (tix < ntiles) tile(pa0, pb0, tix);
+        __syncthreads();
+        int tid2 = tid;
+        asm volatile("" : "+v"(tid2));
+#pragma unroll
+        for (int u = 0; u < RR; ++u) {
+            const unsigned x = (unsigned)min(tid2 + u * kTripleThreads, run - 1);
+            at32(gC, x) = Cs[x];
+        }
+        if (!more) break;
+        // With an odd tile count the next triple's tile 0 went into the
+        // second register set.
+        if (ntiles & 1) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const T ta = pa0[u], tb = pb0[u];
+                pa0[u] = pa1[u];
+                pb0[u] = pb1[u];
+                pa1[u] = ta;
+                pb1[u] = tb;
+            }
+        }
+        __syncthreads();   // the C run has been read out of LDS
+        cur = nxt;
+        Tg = Tn;
+    }
+}
+
 // Step 5: the complementary pair c_ijkn, c_knij (equation (10)) both become
 // their mean.  One thread per C entry; the thread with i < k does the pair.
 template <typename T>

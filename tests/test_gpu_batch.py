@@ -45,6 +45,25 @@ def test_batch_equals_individual_handles_bitwise():
     g.close()
 
 
+def test_batch_of_large_nodes_equals_individual_handles_bitwise():
+    # Nodes of N' = 20..22: in FP64 one facility triple needs more than half a
+    # CU's LDS, so steps 1-3 run one persistent workgroup per CU over the
+    # triples of instances of different sizes.
+    _, _, nodes = _nodes(24, 5, 7, 2, 4)
+    print("batch of 5 nodes, N' =", sorted({n[0].shape[0] for n in nodes}), flush=True)
+    g = Rlt2.batch([n[0] for n in nodes], [n[1] for n in nodes], [n[2] for n in nodes],
+                   [n[3] for n in nodes], trace_level=2)
+    g.ascend(2)
+    for k, (Fs, Ds, Bs, c) in enumerate(nodes):
+        h = Rlt2(Fs, Ds, B0=Bs, constant=c, trace_level=2)
+        h.ascend(2)
+        np.testing.assert_array_equal(h.trace()[0], g.trace_k(k)[0])
+        for x, y in zip(h.lap_values(), g.lap_values_k(k)):
+            np.testing.assert_array_equal(x, y)
+        h.close()
+    g.close()
+
+
 def test_batch_nodes_match_oracle_and_stay_below_optimum():
     F, D, fixes = qapgen.nodes(count=12, parent_N=11, seed=5, m_lo=3, m_hi=5)
     nodes = [subproblem(F, D, fac, loc) for fac, loc in fixes]
