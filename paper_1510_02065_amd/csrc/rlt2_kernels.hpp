@@ -815,12 +815,15 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict
         }
         const long long Tn = Tg + gridDim.x;
         const bool more = Tn < totalTri;
+        // The next triple (when there is none, every "next" load below reads
+        // one entry of this triple's runs: the code stays straight-line).
         const TripleRef<T> nxt = triple_ref<T>(Dd, CC, tri, inst, preWG, K, more ? Tn : Tg);
         T* const hA = nxt.gA;
         T* const hB = nxt.gB;
-        const int hN = nxt.N, hrow = nxt.rowlen, hlast = (nxt.ntiles - 1) * kTripleJT;
-        loadC(nxt.gC, nxt.run, 0);   // registers free again: the next triple's run and tables
-        loadX(nxt.CCk, nxt.N, nxt.i, nxt.k, nxt.p);
+        const int hN = more ? nxt.N : 1, hrow = more ? nxt.rowlen : 1;
+        const int hlast = more ? (nxt.ntiles - 1) * kTripleJT : 0;
+        loadC(nxt.gC, more ? nxt.run : 1, 0);   // registers free again: the next triple's run and tables
+        loadX(nxt.CCk, hN, nxt.i, nxt.k, nxt.p);
         auto tile = [&](T (&ra)[2], T (&rb)[2], int tix) {
             const int j0 = tix * kTripleJT;
             const int len = min(kTripleJT, N - j0) * rowlen;
