@@ -200,14 +200,14 @@ __global__ __launch_bounds__(64) void k_lap_batch(int batch, const int32_t* __re
     int n = (b < batch) ? nv[b] : 0;
     const bool bad = n < 0 || n > SEG;
     if (bad) n = 0;
-    const SegScratch<T, SEG> sc(smem + seg * SegLds<T, SEG>::bytes(SEG), SEG);
+    const SlotScratch<T, SEG, 1> sc(smem + seg * SlotLds<T, SEG, 1>::bytes(SEG), n);
     T* mat = (b < batch && !bad) ? cost + mat_off[b] : nullptr;
     const int64_t vo = (b < batch && !bad) ? vec_off[b] : 0;
     stage_block<T, SEG, 1>(sc.M, mat, n, n, lane);
     wave_sync();
-    const double S = lap_concentrate_seg<T, SEG>(
-        sc, n, (write_residual && n > 0) ? mat : nullptr,
-        (duals && n > 0) ? duals + 4 * vo : nullptr, (assign && n > 0) ? assign + vo : nullptr);
+    const double S = lap_concentrate_flat<T, SEG>(sc, n, (write_residual && n > 0) ? mat : nullptr, n,
+                                                  (duals && n > 0) ? duals + 4 * vo : nullptr,
+                                                  (assign && n > 0) ? assign + vo : nullptr);
     // A quiet NaN written by bit pattern marks a problem that was not solved.
     if (b < batch && lane == 0) value[b] = bad ? __longlong_as_double(0x7ff8000000000000ll) : S;
 }

@@ -1,4 +1,5 @@
-// Linear assignment with canonical dual on gfx950, several columns per lane.
+// Linear assignment with canonical dual on gfx950: the solver of every
+// assignment kernel (the concentrations and the batched qap_lap_solve).
 //
 // Cost concentration (Section 4.1 of arXiv 1510.02065) solves one assignment
 // problem per block of the reduced-cost array, moves its value S to the

@@ -426,7 +426,7 @@ hipError_t launch_batch_seg(hipStream_t st, int batch, const int32_t* n, const i
 {
     if (batch <= 0) return hipSuccess;
     constexpr int LPW = 64 / SEG;
-    const size_t lds = LPW * qap::SegLds<T, SEG>::bytes(SEG);
+    const size_t lds = LPW * qap::SlotLds<T, SEG, 1>::bytes(SEG);
     const unsigned grid = (unsigned)((batch + LPW - 1) / LPW);
     hipLaunchKernelGGL((qap::k_lap_batch<T, SEG>), dim3(grid), dim3(64), lds, st, batch, n, mo, vo, cost,
                        value, duals, assign, wr);
