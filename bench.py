@@ -64,6 +64,7 @@ def parse():
                     help="concentrate every D block instead of each complementary pair once")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the certified FP32 leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched branch-and-bound leg")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="oracle iterations in the CPU baseline (0: pick ~15 s of work)")
     return ap.parse_args()
@@ -83,6 +84,49 @@ def cpu_baseline(F, D, iters):
     o.iterate(iters)
     dt = time.perf_counter() - t
     return iters / dt, iters, oracle.threads()
+
+
+def batched_leg(stream, iters=20):
+    """The batched workload: 256 branch-and-bound nodes cut from one clustered
+    N=24 instance (seed 0) by fixing 2..14 assignments (N' = 10..22), all in
+    one handle, FP64 and certified FP32; iterations launched as HIP graphs
+    after one untimed iteration (which runs the tuner)."""
+    import numpy as np
+    import torch
+
+    import qapgen
+    from paper_1510_02065_amd import Rlt2, subproblem
+
+    F, D, fixes = qapgen.nodes(count=256, parent_N=24, seed=0, m_lo=2, m_hi=14)
+    nodes = [subproblem(F, D, fac, loc) for fac, loc in fixes]
+    sizes = [n[0].shape[0] for n in nodes]
+    laps = int(sum(n * n * (n - 1) * (n - 1) // 2 + n * n + 1 for n in sizes))
+    args = ([n[0] for n in nodes], [n[1] for n in nodes], [n[2] for n in nodes], [n[3] for n in nodes])
+    out = {"workload": f"256 branch-and-bound nodes of clustered N=24 seed 0 (N'={min(sizes)}..{max(sizes)})",
+           "iterations": iters, "laps_per_iteration": laps}
+    lb64 = None
+    for prec in ("fp64", "fp32"):
+        g = Rlt2.batch(*args, precision=prec, stream=stream.cuda_stream)
+        g.ascend(1)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        g.ascend(iters)
+        b.record(stream)
+        b.synchronize()
+        ms = a.elapsed_time(b) / iters
+        leg = {"iters_per_s": 1000.0 / ms, "laps_per_s": laps * 1000.0 / ms, "ms_per_iteration": ms}
+        if prec == "fp64":
+            lb64 = g.bounds()
+        else:
+            _, cert = g.bounds(certified=True)
+            leg["certified_rel_err_vs_fp64_max"] = float(np.max(np.abs(cert - lb64) / np.abs(lb64)))
+            leg["certified_below_fp64"] = bool((cert <= lb64).all())
+        out[prec] = leg
+        g.close()
+    out["speedup_fp32_vs_fp64"] = out["fp32"]["iters_per_s"] / out["fp64"]["iters_per_s"]
+    return out
 
 
 def calibrate_copy():
@@ -260,6 +304,8 @@ def main():
         # moves the whole cost array and is bound by HBM.
         "roofline_sweep": roofline(3),
     }
+    if not args.no_batched:
+        out["batched"] = batched_leg(stream)
     if not args.no_cpu_baseline:
         v, iters, cores = cpu_baseline(F, D, args.cpu_iters)
         out["cpu_baseline"] = {"value": v, "unit": "iters/s", "cores": cores, "kind": "oracle",
