@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <new>
 #include <string>
@@ -61,6 +62,20 @@ struct ClassHost {
     qap::FamilyClass dev() const { return qap::FamilyClass{d_ids, d_pre, (int)ids.size(), total}; }
 };
 
+// Instances of one size in a batch: the per-triple cost sweep of steps 1-3
+// runs one launch per size, with LDS for that size, so a CU holds as many of
+// the small instances' workgroups as fit.
+struct SweepClass {
+    int N = 0;
+    std::vector<int> ids;          // instances of this size
+    std::vector<long long> pre;    // first workgroup (triple) of each, within the launch
+    long long ntri = 0;            // triples of the launch
+    bool per_triple = false;       // one workgroup per triple (else persistent)
+    bool zero_b = false;           // this launch also clears B
+    int* d_ids = nullptr;
+    long long* d_pre = nullptr;
+};
+
 }  // namespace
 
 // ============================================================================
@@ -89,6 +104,8 @@ struct qap_rlt2 {
     long long totalB = 0, totalC = 0, totalD = 0, totalWG = 0;
     std::vector<long long> preB, preC, preWG;
     ClassHost fam[3][4];   // [D, C, B][segment class]
+    std::vector<SweepClass> sweep_cls;   // empty: one sweep launch over every instance
+    bool sweep_per_triple = false;       // that launch: one workgroup per triple (else persistent)
     qap::Inst* dInst = nullptr;
     long long *dPreB = nullptr, *dPreC = nullptr, *dPreWG = nullptr;
     void* dB = nullptr;
@@ -445,6 +462,54 @@ hipError_t launch_batch(hipStream_t st, int seg, int batch, const int32_t* n, co
     }
 }
 
+// Whether a CU holds two workgroups of k_sweep_triple at size N (its
+// registers and its LDS).
+template <typename T>
+bool triple_two_per_cu(int N)
+{
+    int nb = 0;
+    const size_t lds = qap::sweep_triple_lds<T>(N);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, qap::k_sweep_triple<T>, qap::kTripleThreads, lds) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return nb >= 2;
+}
+
+bool triple_two_per_cu_any(const qap_rlt2* h, int N)
+{
+    return h->precision == QAP_FP64 ? triple_two_per_cu<double>(N) : triple_two_per_cu<float>(N);
+}
+
+// Steps 1-3 over `ntri` triples of the instances ids[0..K) (all instances
+// when ids is null), whose triples start at workgroups pre[0..K), laid out in
+// LDS for size N.  When a CU holds only one triple's workgroup, one persistent
+// workgroup per CU walks the triples and overlaps each triple's start with the
+// previous one's tiles; when it holds two (per_triple), one workgroup per
+// triple lets the hardware overlap them.  The launch clears B[0..zeroB); a
+// per-triple launch clears one entry per thread, so zeroB <= ntri *
+// kTripleThreads there.
+template <typename T>
+hipError_t launch_triple(qap_rlt2* h, const long long* pre, const int* ids, int K, long long ntri, int N,
+                         bool per_triple, long long zeroB)
+{
+    T* B = static_cast<T*>(h->dB);
+    T* D = static_cast<T*>(h->dD);
+    const T* CC = static_cast<const T*>(h->dCC);
+    const size_t lds = qap::sweep_triple_lds<T>(N);
+    if (per_triple) {
+        if (zeroB > ntri * qap::kTripleThreads) return hipErrorInvalidConfiguration;
+        hipLaunchKernelGGL((qap::k_sweep_triple<T>), dim3((unsigned)ntri), dim3(qap::kTripleThreads), lds, h->stream,
+                           D, CC, B, h->dTri, h->dInst, pre, ids, K, zeroB);
+    } else {
+        const long long grid = std::min<long long>(ntri, h->num_cu);
+        hipLaunchKernelGGL((qap::k_sweep_triple_p<T>), dim3((unsigned)grid), dim3(qap::kTripleThreads), lds,
+                           h->stream, D, CC, B, h->dTri, h->dInst, pre, ids, K, zeroB, ntri, N);
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t enqueue_step(qap_rlt2* h, int step)
 {
@@ -466,20 +531,15 @@ hipError_t enqueue_step(qap_rlt2* h, int step)
             return hipGetLastError();
         }
         if (h->sweep_kind == 2) {
-            // When a CU holds only one triple's workgroup, one persistent
-            // workgroup per CU walks the triples and overlaps each triple's
-            // start with the previous one's tiles; when it holds two, one
-            // workgroup per triple lets the hardware overlap them.
-            const size_t lds = qap::sweep_triple_lds<T>(h->Nmax);
-            if (h->lds_limit / lds >= 2) {
-                hipLaunchKernelGGL((qap::k_sweep_triple<T>), dim3((unsigned)h->totalWG), dim3(qap::kTripleThreads), lds,
-                                   st, D, CC, B, h->dTri, h->dInst, h->dPreWG, h->K, h->totalB);
-            } else {
-                const long long grid = std::min<long long>(h->totalWG, h->num_cu);
-                hipLaunchKernelGGL((qap::k_sweep_triple_p<T>), dim3((unsigned)grid), dim3(qap::kTripleThreads), lds,
-                                   st, D, CC, B, h->dTri, h->dInst, h->dPreWG, h->K, h->totalB, h->totalWG, h->Nmax);
+            if (h->sweep_cls.empty())
+                return launch_triple<T>(h, h->dPreWG, nullptr, h->K, h->totalWG, h->Nmax, h->sweep_per_triple,
+                                        h->totalB);
+            for (const SweepClass& c : h->sweep_cls) {
+                e = launch_triple<T>(h, c.d_pre, c.d_ids, (int)c.ids.size(), c.ntri, c.N, c.per_triple,
+                                     c.zero_b ? h->totalB : 0);
+                if (e != hipSuccess) return e;
             }
-            return hipGetLastError();
+            return hipSuccess;
         }
         const size_t lds = (size_t)6 * h->Nmax * h->Nmax * sizeof(T);
         if (lds <= h->lds_limit)
@@ -583,6 +643,10 @@ void release(qap_rlt2* h)
             if (c.d_ids) (void)hipFree(c.d_ids);
             if (c.d_pre) (void)hipFree(c.d_pre);
         }
+    for (auto& c : h->sweep_cls) {
+        if (c.d_ids) (void)hipFree(c.d_ids);
+        if (c.d_pre) (void)hipFree(c.d_pre);
+    }
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
 
@@ -763,6 +827,36 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
             h->totalD += ((nC / 2) * n2 * n2 + align_elems - 1) / align_elems * align_elems;
         h->totalWG += h->sweep_kind == 2 ? (long long)I.ntri : 8LL * ((I.ntri + 7) / 8) * I.wpt;
     }
+    // One sweep launch per instance size when a batch mixes sizes; the launch
+    // of the largest size that can clear B does so.
+    if (h->sweep_kind == 2) {
+        h->sweep_per_triple = triple_two_per_cu_any(h, h->Nmax) && h->totalB <= h->totalWG * qap::kTripleThreads;
+        std::vector<int> sizes(Ns, Ns + count);
+        std::sort(sizes.begin(), sizes.end(), std::greater<int>());
+        sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+        if (sizes.size() > 1) {
+            for (int N : sizes) {
+                SweepClass c;
+                c.N = N;
+                c.per_triple = triple_two_per_cu_any(h, N);
+                for (int k = 0; k < count; ++k)
+                    if ((int)Ns[k] == N) {
+                        c.ids.push_back(k);
+                        c.pre.push_back(c.ntri);
+                        c.ntri += h->inst[k].ntri;
+                    }
+                h->sweep_cls.push_back(std::move(c));
+            }
+            bool placed = false;
+            for (SweepClass& c : h->sweep_cls) {
+                if (!c.per_triple || c.ntri * qap::kTripleThreads >= h->totalB) {
+                    c.zero_b = placed = true;
+                    break;
+                }
+            }
+            if (!placed) h->sweep_cls.clear();
+        }
+    }
     // Segment-size classes of the three families.
     for (int f = 0; f < 3; ++f) {
         for (int k = 0; k < count; ++k) {
@@ -836,6 +930,10 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
     CK(upload(&h->dPreB, h->preB, h->stream));
     CK(upload(&h->dPreC, h->preC, h->stream));
     CK(upload(&h->dPreWG, h->preWG, h->stream));
+    for (auto& c : h->sweep_cls) {
+        CK(upload(&c.d_ids, c.ids, h->stream));
+        CK(upload(&c.d_pre, c.pre, h->stream));
+    }
     for (auto& f : h->fam)
         for (auto& c : f) {
             if (c.ids.empty()) continue;

@@ -550,14 +550,16 @@ template <typename T>
 __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__ Dd, const T* __restrict__ CC,
                                                                  T* __restrict__ B, const int* __restrict__ tri,
                                                                  const Inst* __restrict__ inst,
-                                                                 const long long* __restrict__ preWG, int K,
+                                                                 const long long* __restrict__ preWG,
+                                                                 const int* __restrict__ ids, int K,
                                                                  long long totalB)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const long long gx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gx < totalB) B[gx] = (T)0;
-    const Inst I = inst[find_seg(preWG, K, (long long)blockIdx.x)];
-    const int t = (int)((long long)blockIdx.x - I.wg0);
+    const int s = find_seg(preWG, K, (long long)blockIdx.x);
+    const Inst I = inst[ids ? ids[s] : s];
+    const int t = (int)((long long)blockIdx.x - preWG[s]);
     if (t >= I.ntri) return;   // whole workgroup
     const int N = I.N, n1 = N - 1, n2 = N - 2;
     const int NN = N * N;
@@ -708,10 +710,11 @@ struct TripleRef {
 template <typename T>
 __device__ __forceinline__ TripleRef<T> triple_ref(T* Dd, const T* CC, const int* __restrict__ tri,
                                                    const Inst* __restrict__ inst, const long long* __restrict__ preWG,
-                                                   int K, long long Tg)
+                                                   const int* __restrict__ ids, int K, long long Tg)
 {
-    const Inst I = inst[find_seg(preWG, K, Tg)];
-    const int t = (int)(Tg - I.wg0);
+    const int s = find_seg(preWG, K, Tg);
+    const Inst I = inst[ids ? ids[s] : s];
+    const int t = (int)(Tg - preWG[s]);
     TripleRef<T> r;
     r.N = I.N;
     r.n1 = r.N - 1;
@@ -737,7 +740,8 @@ template <typename T>
 __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict__ Dd, const T* __restrict__ CC,
                                                                    T* __restrict__ B, const int* __restrict__ tri,
                                                                    const Inst* __restrict__ inst,
-                                                                   const long long* __restrict__ preWG, int K,
+                                                                   const long long* __restrict__ preWG,
+                                                                   const int* __restrict__ ids, int K,
                                                                    long long totalB, long long totalTri, int Nmax)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -794,7 +798,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict
         }
     };
 
-    TripleRef<T> cur = triple_ref<T>(Dd, CC, tri, inst, preWG, K, Tg);
+    TripleRef<T> cur = triple_ref<T>(Dd, CC, tri, inst, preWG, ids, K, Tg);
     T pa0[2], pb0[2], pa1[2], pb1[2];
     loadC(cur.gC, cur.run, 0);
     loadX(cur.CCk, cur.N, cur.i, cur.k, cur.p);
@@ -817,7 +821,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict
         const bool more = Tn < totalTri;
         // The next triple (when there is none, every "next" load below reads
         // one entry of this triple's runs: the code stays straight-line).
-        const TripleRef<T> nxt = triple_ref<T>(Dd, CC, tri, inst, preWG, K, more ? Tn : Tg);
+        const TripleRef<T> nxt = triple_ref<T>(Dd, CC, tri, inst, preWG, ids, K, more ? Tn : Tg);
         T* const hA = nxt.gA;
         T* const hB = nxt.gB;
         const int hN = more ? nxt.N : 1, hrow = more ? nxt.rowlen : 1;

@@ -25,15 +25,17 @@ def _nodes(parent_N, count, seed, m_lo, m_hi):
     return F, D, [subproblem(F, D, fac, loc) for fac, loc in fixes]
 
 
-def test_batch_equals_individual_handles_bitwise():
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_equals_individual_handles_bitwise(precision):
+    # Nodes of N' = 6..10: steps 1-3 run one launch per node size.
     _, _, nodes = _nodes(12, 20, 3, 2, 6)
-    print("batch of 20 nodes, N' =", sorted({n[0].shape[0] for n in nodes}), flush=True)
+    print(f"batch of 20 nodes {precision}, N' =", sorted({n[0].shape[0] for n in nodes}), flush=True)
     g = Rlt2.batch([n[0] for n in nodes], [n[1] for n in nodes], [n[2] for n in nodes],
-                   [n[3] for n in nodes], trace_level=2)
+                   [n[3] for n in nodes], precision=precision, trace_level=2)
     g.ascend(4)
     lbs = g.bounds()
     for k, (Fs, Ds, Bs, c) in enumerate(nodes):
-        h = Rlt2(Fs, Ds, B0=Bs, constant=c, trace_level=2)
+        h = Rlt2(Fs, Ds, B0=Bs, constant=c, precision=precision, trace_level=2)
         h.ascend(4)
         np.testing.assert_array_equal(h.trace()[0], g.trace_k(k)[0])
         assert h.bound()[0] == lbs[k]
@@ -46,9 +48,9 @@ def test_batch_equals_individual_handles_bitwise():
 
 
 def test_batch_of_large_nodes_equals_individual_handles_bitwise():
-    # Nodes of N' = 20..22: in FP64 one facility triple needs more than half a
-    # CU's LDS, so steps 1-3 run one persistent workgroup per CU over the
-    # triples of instances of different sizes.
+    # Nodes of N' = 20..22: in FP64 a CU holds one facility triple's
+    # workgroup, so steps 1-3 run one persistent workgroup per CU, one launch
+    # per node size.
     _, _, nodes = _nodes(24, 5, 7, 2, 4)
     print("batch of 5 nodes, N' =", sorted({n[0].shape[0] for n in nodes}), flush=True)
     g = Rlt2.batch([n[0] for n in nodes], [n[1] for n in nodes], [n[2] for n in nodes],
