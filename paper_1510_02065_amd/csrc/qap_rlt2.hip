@@ -70,7 +70,7 @@ struct SweepClass {
     std::vector<int> ids;          // instances of this size
     std::vector<long long> pre;    // first workgroup (triple) of each, within the launch
     long long ntri = 0;            // triples of the launch
-    bool per_triple = false;       // one workgroup per triple (else persistent)
+    int nt = 0;                    // threads of a per-triple workgroup (0: persistent kernel)
     bool zero_b = false;           // this launch also clears B
     int* d_ids = nullptr;
     long long* d_pre = nullptr;
@@ -105,7 +105,7 @@ struct qap_rlt2 {
     std::vector<long long> preB, preC, preWG;
     ClassHost fam[3][4];   // [D, C, B][segment class]
     std::vector<SweepClass> sweep_cls;   // empty: one sweep launch over every instance
-    bool sweep_per_triple = false;       // that launch: one workgroup per triple (else persistent)
+    int sweep_nt = 0;                    // that launch: threads of a per-triple workgroup (0: persistent)
     qap::Inst* dInst = nullptr;
     long long *dPreB = nullptr, *dPreC = nullptr, *dPreWG = nullptr;
     void* dB = nullptr;
@@ -462,47 +462,72 @@ hipError_t launch_batch(hipStream_t st, int seg, int batch, const int32_t* n, co
     }
 }
 
-// Whether a CU holds two workgroups of k_sweep_triple at size N (its
-// registers and its LDS).
-template <typename T>
-bool triple_two_per_cu(int N)
+// Workgroups of k_sweep_triple<T, NT> a CU holds at size N (its registers
+// and its LDS); 0 when the triple does not fit NT threads.
+template <typename T, int NT>
+int triple_per_cu(int N)
 {
+    const size_t lds = qap::sweep_triple_lds<T, NT>(N);
+    if (lds == (size_t)-1) return 0;
     int nb = 0;
-    const size_t lds = qap::sweep_triple_lds<T>(N);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, qap::k_sweep_triple<T>, qap::kTripleThreads, lds) !=
-        hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, qap::k_sweep_triple<T, NT>, NT, lds) != hipSuccess) {
         (void)hipGetLastError();
-        return false;
+        return 0;
     }
-    return nb >= 2;
+    return nb;
 }
 
-bool triple_two_per_cu_any(const qap_rlt2* h, int N)
+// Threads of a per-triple workgroup for size N, or 0 for the persistent
+// kernel (a CU holds one triple's workgroup at most): of the two workgroup
+// sizes with two or more workgroups per CU, the one with more resident waves,
+// the smaller on a tie.
+template <typename T>
+int triple_threads(int N)
 {
-    return h->precision == QAP_FP64 ? triple_two_per_cu<double>(N) : triple_two_per_cu<float>(N);
+    const int small = triple_per_cu<T, qap::kTripleThreadsSmall>(N);
+    const int large = triple_per_cu<T, qap::kTripleThreads>(N);
+    const long long ws = small >= 2 ? (long long)small * qap::kTripleThreadsSmall : 0;
+    const long long wl = large >= 2 ? (long long)large * qap::kTripleThreads : 0;
+    if (ws == 0 && wl == 0) return 0;
+    return wl > ws ? qap::kTripleThreads : qap::kTripleThreadsSmall;
+}
+
+int triple_threads_any(const qap_rlt2* h, int N)
+{
+    return h->precision == QAP_FP64 ? triple_threads<double>(N) : triple_threads<float>(N);
 }
 
 // Steps 1-3 over `ntri` triples of the instances ids[0..K) (all instances
 // when ids is null), whose triples start at workgroups pre[0..K), laid out in
 // LDS for size N.  When a CU holds only one triple's workgroup, one persistent
 // workgroup per CU walks the triples and overlaps each triple's start with the
-// previous one's tiles; when it holds two (per_triple), one workgroup per
-// triple lets the hardware overlap them.  The launch clears B[0..zeroB); a
-// per-triple launch clears one entry per thread, so zeroB <= ntri *
-// kTripleThreads there.
+// previous one's tiles; when it holds two or more (nt > 0), one workgroup of
+// nt threads per triple lets the hardware overlap them.  The launch clears
+// B[0..zeroB); a per-triple launch clears one entry per thread, so zeroB <=
+// ntri * nt there.
 template <typename T>
-hipError_t launch_triple(qap_rlt2* h, const long long* pre, const int* ids, int K, long long ntri, int N,
-                         bool per_triple, long long zeroB)
+hipError_t launch_triple(qap_rlt2* h, const long long* pre, const int* ids, int K, long long ntri, int N, int nt,
+                         long long zeroB)
 {
     T* B = static_cast<T*>(h->dB);
     T* D = static_cast<T*>(h->dD);
     const T* CC = static_cast<const T*>(h->dCC);
-    const size_t lds = qap::sweep_triple_lds<T>(N);
-    if (per_triple) {
-        if (zeroB > ntri * qap::kTripleThreads) return hipErrorInvalidConfiguration;
-        hipLaunchKernelGGL((qap::k_sweep_triple<T>), dim3((unsigned)ntri), dim3(qap::kTripleThreads), lds, h->stream,
-                           D, CC, B, h->dTri, h->dInst, pre, ids, K, zeroB);
+    if (nt > 0) {
+        if (zeroB > ntri * nt) return hipErrorInvalidConfiguration;
+        if (nt == qap::kTripleThreadsSmall) {
+            const size_t lds = qap::sweep_triple_lds<T, qap::kTripleThreadsSmall>(N);
+            if (lds == (size_t)-1) return hipErrorInvalidConfiguration;
+            hipLaunchKernelGGL((qap::k_sweep_triple<T, qap::kTripleThreadsSmall>), dim3((unsigned)ntri),
+                               dim3(qap::kTripleThreadsSmall), lds, h->stream, D, CC, B, h->dTri, h->dInst, pre, ids,
+                               K, zeroB);
+        } else {
+            const size_t lds = qap::sweep_triple_lds<T>(N);
+            hipLaunchKernelGGL((qap::k_sweep_triple<T, qap::kTripleThreads>), dim3((unsigned)ntri),
+                               dim3(qap::kTripleThreads), lds, h->stream, D, CC, B, h->dTri, h->dInst, pre, ids, K,
+                               zeroB);
+        }
     } else {
+        const size_t lds = qap::sweep_triple_lds<T>(N);
         const long long grid = std::min<long long>(ntri, h->num_cu);
         hipLaunchKernelGGL((qap::k_sweep_triple_p<T>), dim3((unsigned)grid), dim3(qap::kTripleThreads), lds,
                            h->stream, D, CC, B, h->dTri, h->dInst, pre, ids, K, zeroB, ntri, N);
@@ -532,10 +557,9 @@ hipError_t enqueue_step(qap_rlt2* h, int step)
         }
         if (h->sweep_kind == 2) {
             if (h->sweep_cls.empty())
-                return launch_triple<T>(h, h->dPreWG, nullptr, h->K, h->totalWG, h->Nmax, h->sweep_per_triple,
-                                        h->totalB);
+                return launch_triple<T>(h, h->dPreWG, nullptr, h->K, h->totalWG, h->Nmax, h->sweep_nt, h->totalB);
             for (const SweepClass& c : h->sweep_cls) {
-                e = launch_triple<T>(h, c.d_pre, c.d_ids, (int)c.ids.size(), c.ntri, c.N, c.per_triple,
+                e = launch_triple<T>(h, c.d_pre, c.d_ids, (int)c.ids.size(), c.ntri, c.N, c.nt,
                                      c.zero_b ? h->totalB : 0);
                 if (e != hipSuccess) return e;
             }
@@ -830,7 +854,8 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
     // One sweep launch per instance size when a batch mixes sizes; the launch
     // of the largest size that can clear B does so.
     if (h->sweep_kind == 2) {
-        h->sweep_per_triple = triple_two_per_cu_any(h, h->Nmax) && h->totalB <= h->totalWG * qap::kTripleThreads;
+        h->sweep_nt = triple_threads_any(h, h->Nmax);
+        if (h->totalB > h->totalWG * h->sweep_nt) h->sweep_nt = 0;
         std::vector<int> sizes(Ns, Ns + count);
         std::sort(sizes.begin(), sizes.end(), std::greater<int>());
         sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
@@ -838,7 +863,7 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
             for (int N : sizes) {
                 SweepClass c;
                 c.N = N;
-                c.per_triple = triple_two_per_cu_any(h, N);
+                c.nt = triple_threads_any(h, N);
                 for (int k = 0; k < count; ++k)
                     if ((int)Ns[k] == N) {
                         c.ids.push_back(k);
@@ -849,7 +874,7 @@ qap_status qap_rlt2_batch_create(int count, const int32_t* Ns, const double* con
             }
             bool placed = false;
             for (SweepClass& c : h->sweep_cls) {
-                if (!c.per_triple || c.ntri * qap::kTripleThreads >= h->totalB) {
+                if (c.nt == 0 || c.ntri * c.nt >= h->totalB) {
                     c.zero_b = placed = true;
                     break;
                 }

@@ -525,29 +525,34 @@ __device__ __forceinline__ T& at32(T* base, unsigned idx)
 // the C run, the tables and the first two tiles are all requested before
 // anything is written to LDS, and while a tile is processed the rows of the
 // next two tiles are in flight.
+// A workgroup has NT = kTripleThreads threads, or kTripleThreadsSmall for
+// instances whose triple fits it (then a CU holds more triples at once).
 constexpr int kTripleThreads = 1024;
+constexpr int kTripleThreadsSmall = 512;
 constexpr int kTripleJT = 2;
-// Entries of the C run per thread: N (N-1) (N-2) <= kTripleRunRegs * kTripleThreads
-// (N <= 25 in FP64, N <= 32 in FP32), loaded kTripleRunChunk at a time.
+// Entries of the C run per thread: N (N-1) (N-2) <= kTripleRunRegs * NT
+// (N <= 25 in FP64, N <= 32 in FP32 at 1024 threads), loaded kTripleRunChunk
+// at a time.
 template <typename T>
 constexpr int kTripleRunRegs = sizeof(T) == 8 ? 14 : 30;
 template <typename T>
 constexpr int kTripleRunChunk = sizeof(T) == 8 ? 14 : 10;
 
-// LDS bytes of k_sweep_triple at size N; (size_t)-1 when a location tile, the
-// C run or the tables exceed what the kernel holds per thread.
-template <typename T>
+// LDS bytes of k_sweep_triple at size N with NT threads; (size_t)-1 when a
+// location tile, the C run or the tables exceed what the kernel holds per
+// thread.
+template <typename T, int NT = kTripleThreads>
 __host__ __device__ inline size_t sweep_triple_lds(int N)
 {
     const size_t run = (size_t)N * (N - 1) * (N - 2);
-    if ((size_t)kTripleJT * (N - 1) * (N - 2) > 2 * (size_t)kTripleThreads) return (size_t)-1;
-    if (run > (size_t)kTripleRunRegs<T> * kTripleThreads) return (size_t)-1;
-    if ((size_t)6 * N * N > 6 * (size_t)kTripleThreads) return (size_t)-1;
+    if ((size_t)kTripleJT * (N - 1) * (N - 2) > 2 * (size_t)NT) return (size_t)-1;
+    if (run > (size_t)kTripleRunRegs<T> * NT) return (size_t)-1;
+    if ((size_t)6 * N * N > 6 * (size_t)NT) return (size_t)-1;
     return (run + (size_t)6 * N * N + (size_t)2 * kTripleJT * (N - 1) * (N - 2)) * sizeof(T);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__ Dd, const T* __restrict__ CC,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_sweep_triple(T* __restrict__ Dd, const T* __restrict__ CC,
                                                                  T* __restrict__ B, const int* __restrict__ tri,
                                                                  const Inst* __restrict__ inst,
                                                                  const long long* __restrict__ preWG,
@@ -587,17 +592,17 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__
     T cr[RC];
     auto loadC = [&](int c0) {
 #pragma unroll
-        for (int u = 0; u < RC; ++u) cr[u] = at32(gC, (unsigned)min(tid + (c0 + u) * kTripleThreads, run - 1));
+        for (int u = 0; u < RC; ++u) cr[u] = at32(gC, (unsigned)min(tid + (c0 + u) * NT, run - 1));
     };
     auto putC = [&](int c0) {
 #pragma unroll
-        for (int u = 0; u < RC; ++u) Cs[min(tid + (c0 + u) * kTripleThreads, run - 1)] = cr[u];
+        for (int u = 0; u < RC; ++u) Cs[min(tid + (c0 + u) * NT, run - 1)] = cr[u];
     };
     loadC(0);
     T xr[6];
 #pragma unroll
     for (int u = 0; u < 6; ++u) {
-        const int x = min(tid + u * kTripleThreads, 6 * NN - 1);
+        const int x = min(tid + u * NT, 6 * NN - 1);
         const int m = x / NN, r = x - m * NN;
         const int a = r / N, b = r - a * N;
         const int f1 = m < 2 ? i : m < 4 ? k : p;
@@ -611,7 +616,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__
         T* __restrict__ tB = gB + (long long)j0 * rowlen;
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const unsigned x = (unsigned)min(tid + u * kTripleThreads, len - 1);
+            const unsigned x = (unsigned)min(tid + u * NT, len - 1);
             ra[u] = at32(tA, x);
             rb[u] = at32(tB, x);
         }
@@ -621,7 +626,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__
     fetch(pa1, pb1, 1);
     putC(0);
 #pragma unroll
-    for (int u = 0; u < 6; ++u) X[min(tid + u * kTripleThreads, 6 * NN - 1)] = xr[u];
+    for (int u = 0; u < 6; ++u) X[min(tid + u * NT, 6 * NN - 1)] = xr[u];
 #pragma unroll
     for (int c0 = RC; c0 < RR; c0 += RC) {   // FP32 only: the rest of the run
         loadC(c0);
@@ -639,13 +644,13 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__
         __syncthreads();   // previous tile written back (C and X in place)
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int x = min(tid + u * kTripleThreads, len - 1);
+            const int x = min(tid + u * NT, len - 1);
             As[x] = ra[u];
             Bs[x] = rb[u];
         }
         __syncthreads();
         fetch(ra, rb, tix + 2);
-        for (int g = tid; g < len; g += kTripleThreads) {
+        for (int g = tid; g < len; g += NT) {
             const int jl = g / rowlen, r = g - jl * rowlen;
             const int j = j0 + jl;
             const int nc = r / n2, qc = r - nc * n2;   // n' (skipping j), q'' (skipping j and n)
@@ -667,7 +672,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const unsigned x = (unsigned)min(tid + u * kTripleThreads, len - 1);
+            const unsigned x = (unsigned)min(tid + u * NT, len - 1);
             at32(tA, x) = As[x];
             at32(tB, x) = Bs[x];
         }
@@ -685,7 +690,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__
     asm volatile("" : "+v"(tid2));
 #pragma unroll
     for (int u = 0; u < RR; ++u) {
-        const unsigned x = (unsigned)min(tid2 + u * kTripleThreads, run - 1);
+        const unsigned x = (unsigned)min(tid2 + u * NT, run - 1);
         at32(gC, x) = Cs[x];
     }
 }
@@ -696,8 +701,8 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple(T* __restrict__
 // and tables are in LDS, the next triple's are requested into the registers
 // they came through, and the two-tiles-ahead prefetch runs on into the next
 // triple's first tiles, so a triple's start overlaps the previous one's tiles.
-// LDS is laid out for the largest instance.  Same arithmetic and order as
-// k_sweep_triple.
+// LDS is laid out for size Nmax, the largest instance of the launch.  Same
+// arithmetic and order as k_sweep_triple.
 template <typename T>
 struct TripleRef {
     int N, n1, n2, NN, run, rowlen, ntiles, i, k, p;

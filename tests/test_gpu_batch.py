@@ -47,17 +47,19 @@ def test_batch_equals_individual_handles_bitwise(precision):
     g.close()
 
 
-def test_batch_of_large_nodes_equals_individual_handles_bitwise():
-    # Nodes of N' = 20..22: in FP64 a CU holds one facility triple's
-    # workgroup, so steps 1-3 run one persistent workgroup per CU, one launch
-    # per node size.
-    _, _, nodes = _nodes(24, 5, 7, 2, 4)
-    print("batch of 5 nodes, N' =", sorted({n[0].shape[0] for n in nodes}), flush=True)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_of_large_nodes_equals_individual_handles_bitwise(precision):
+    # Nodes of N' = 17..22, one steps 1-3 launch per node size.  In FP64 a CU
+    # holds one 1024-thread triple workgroup, so N' >= 20 runs one persistent
+    # workgroup per CU and smaller nodes 512-thread workgroups per triple; in
+    # FP32 the larger nodes run two 1024-thread workgroups per CU.
+    _, _, nodes = _nodes(24, 6, 7, 2, 7)
+    print(f"batch of 6 nodes {precision}, N' =", sorted({n[0].shape[0] for n in nodes}), flush=True)
     g = Rlt2.batch([n[0] for n in nodes], [n[1] for n in nodes], [n[2] for n in nodes],
-                   [n[3] for n in nodes], trace_level=2)
+                   [n[3] for n in nodes], precision=precision, trace_level=2)
     g.ascend(2)
     for k, (Fs, Ds, Bs, c) in enumerate(nodes):
-        h = Rlt2(Fs, Ds, B0=Bs, constant=c, trace_level=2)
+        h = Rlt2(Fs, Ds, B0=Bs, constant=c, precision=precision, trace_level=2)
         h.ascend(2)
         np.testing.assert_array_equal(h.trace()[0], g.trace_k(k)[0])
         for x, y in zip(h.lap_values(), g.lap_values_k(k)):
