@@ -63,8 +63,8 @@ struct ClassHost {
 };
 
 // Instances of one size in a batch: the per-triple cost sweep of steps 1-3
-// runs one launch per size, with LDS for that size, so a CU holds as many of
-// the small instances' workgroups as fit.
+// runs one launch per size, with the workgroup width and LDS for that size,
+// so a CU holds as many of the small instances' workgroups as fit.
 struct SweepClass {
     int N = 0;
     std::vector<int> ids;          // instances of this size

@@ -551,20 +551,20 @@ __host__ __device__ inline size_t sweep_triple_lds(int N)
     return (run + (size_t)6 * N * N + (size_t)2 * kTripleJT * (N - 1) * (N - 2)) * sizeof(T);
 }
 
+// Workgroup b takes triple b - pre[s] of instance ids[s] (of instance s when
+// ids is null), s the last of the K prefix entries with pre[s] <= b.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_sweep_triple(T* __restrict__ Dd, const T* __restrict__ CC,
-                                                                 T* __restrict__ B, const int* __restrict__ tri,
-                                                                 const Inst* __restrict__ inst,
-                                                                 const long long* __restrict__ preWG,
-                                                                 const int* __restrict__ ids, int K,
-                                                                 long long totalB)
+                                                     T* __restrict__ B, const int* __restrict__ tri,
+                                                     const Inst* __restrict__ inst, const long long* __restrict__ pre,
+                                                     const int* __restrict__ ids, int K, long long totalB)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const long long gx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gx < totalB) B[gx] = (T)0;
-    const int s = find_seg(preWG, K, (long long)blockIdx.x);
+    const int s = find_seg(pre, K, (long long)blockIdx.x);
     const Inst I = inst[ids ? ids[s] : s];
-    const int t = (int)((long long)blockIdx.x - preWG[s]);
+    const int t = (int)((long long)blockIdx.x - pre[s]);
     if (t >= I.ntri) return;   // whole workgroup
     const int N = I.N, n1 = N - 1, n2 = N - 2;
     const int NN = N * N;
@@ -714,12 +714,12 @@ struct TripleRef {
 
 template <typename T>
 __device__ __forceinline__ TripleRef<T> triple_ref(T* Dd, const T* CC, const int* __restrict__ tri,
-                                                   const Inst* __restrict__ inst, const long long* __restrict__ preWG,
+                                                   const Inst* __restrict__ inst, const long long* __restrict__ pre,
                                                    const int* __restrict__ ids, int K, long long Tg)
 {
-    const int s = find_seg(preWG, K, Tg);
+    const int s = find_seg(pre, K, Tg);
     const Inst I = inst[ids ? ids[s] : s];
-    const int t = (int)(Tg - preWG[s]);
+    const int t = (int)(Tg - pre[s]);
     TripleRef<T> r;
     r.N = I.N;
     r.n1 = r.N - 1;
@@ -745,7 +745,7 @@ template <typename T>
 __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict__ Dd, const T* __restrict__ CC,
                                                                    T* __restrict__ B, const int* __restrict__ tri,
                                                                    const Inst* __restrict__ inst,
-                                                                   const long long* __restrict__ preWG,
+                                                                   const long long* __restrict__ pre,
                                                                    const int* __restrict__ ids, int K,
                                                                    long long totalB, long long totalTri, int Nmax)
 {
@@ -803,7 +803,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict
         }
     };
 
-    TripleRef<T> cur = triple_ref<T>(Dd, CC, tri, inst, preWG, ids, K, Tg);
+    TripleRef<T> cur = triple_ref<T>(Dd, CC, tri, inst, pre, ids, K, Tg);
     T pa0[2], pb0[2], pa1[2], pb1[2];
     loadC(cur.gC, cur.run, 0);
     loadX(cur.CCk, cur.N, cur.i, cur.k, cur.p);
@@ -826,7 +826,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict
         const bool more = Tn < totalTri;
         // The next triple (when there is none, every "next" load below reads
         // one entry of this triple's runs: the code stays straight-line).
-        const TripleRef<T> nxt = triple_ref<T>(Dd, CC, tri, inst, preWG, ids, K, more ? Tn : Tg);
+        const TripleRef<T> nxt = triple_ref<T>(Dd, CC, tri, inst, pre, ids, K, more ? Tn : Tg);
         T* const hA = nxt.gA;
         T* const hB = nxt.gB;
         const int hN = more ? nxt.N : 1, hrow = more ? nxt.rowlen : 1;
