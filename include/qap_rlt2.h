@@ -56,9 +56,21 @@ typedef enum {
 
 typedef enum {
     QAP_FP64 = 0,            /* all reduced costs and transfers in FP64         */
-    QAP_FP32_CERTIFIED = 1   /* FP32 reduced costs, every receiving write
+    QAP_FP32_CERTIFIED = 1,  /* FP32 reduced costs, every receiving write
                                 rounded toward -inf, FP64 bound and FP64
-                                certification (see qap_rlt2_certify)           */
+                                certification (see qap_rlt2_certify): the
+                                stored state never represents more than the
+                                true objective, so the bound is proven valid;
+                                the directed roundings lower the trajectory
+                                by about one FP32 ulp per write               */
+    QAP_FP32_NEAREST = 2     /* FP32 reduced costs, every receiving write
+                                computed in FP64 and rounded to nearest once,
+                                FP64 bound and FP64 certification: follows the
+                                FP64 trajectory without a systematic drift;
+                                the certification removes any negative stored
+                                entry, and the state's represented objective
+                                differs from the true one only by accumulated
+                                FP32 roundings                                */
 } qap_precision;
 
 typedef struct {
@@ -88,12 +100,21 @@ typedef struct {
                          equal and a concentration keeps them so, so the state
                          is bit for bit that of 0, which stores and
                          concentrates every block, with half the memory     */
+    double K;          /* stop rule of Algorithm 1: an instance stops once
+                         LB' / UB < K (progress below K), 0 = never on progress */
+    double UB;         /* upper bound of the stop rule: an instance stops once
+                         LB >= UB; UB <= 0 turns the whole rule off (default) */
+    int level;         /* 2 (default): the level-2 RLT dual (B, C, D);
+                         1: the level-1 dual (B and C only, no D: an iteration
+                         is steps 1, 5, 6, 7 and 8), the dual of the strong
+                         branching of Section 6                              */
 } qap_rlt2_opts;
 
 typedef struct qap_rlt2 qap_rlt2;
 
 /* Fill *opts with the defaults (FP64, current device, own stream,
- * trace_level 1, use_graph 1, autotune 1, no tune cache, complementary 1). */
+ * trace_level 1, use_graph 1, autotune 1, no tune cache, complementary 1,
+ * no stop rule, level 2). */
 qap_status qap_rlt2_default_opts(qap_rlt2_opts* opts);
 
 /* Create a dual-ascent state for the QAP of equation (1) with flows F and
@@ -112,7 +133,9 @@ qap_status qap_rlt2_create_ex(int N, const double* F, const double* D,
                               const double* B0, double constant,
                               const qap_rlt2_opts* opts, qap_rlt2** out);
 
-/* Run `iters` >= 0 iterations of the Algorithm 1 loop body:
+/* Run `iters` >= 0 iterations of the Algorithm 1 loop body (at most: an
+ * instance whose stop rule has fired runs no further iteration and keeps its
+ * state, and the call returns early once every instance has stopped):
  *   1. spread B -> C: c_ijkn += b_ij / (N-1), then b = 0        (Section 4.2)
  *   2. spread C -> D: d_ijknpq += c_ijkn / (N-2), then c = 0     (Section 4.2)
  *   3. transfer among the six complementary D coefficients of equation (11):
@@ -147,8 +170,8 @@ qap_status qap_rlt2_step(qap_rlt2* h, int step);
  * state, whatever the signs of the stored reduced costs. */
 qap_status qap_rlt2_certify(qap_rlt2* h, double* certified);
 
-/* Bound after the most recent iteration and the number of iterations run
- * (iteration 0 counts as 0; each loop iteration adds 1). */
+/* Bound after the most recent iteration and the number of loop iterations
+ * instance 0 has run (iteration 0 counts as 0; each loop iteration adds 1). */
 qap_status qap_rlt2_bound(qap_rlt2* h, double* lb, int64_t* iterations);
 
 /* Per-iteration trace (trace_level >= 1): entries t = 0 .. *count-1 hold LB
@@ -230,8 +253,9 @@ qap_status qap_subproblem(int N, const double* F, const double* D, int m, const 
  * vec_off problem b's vectors start at element vec_off[b] of `assign` and at
  *         element 4*vec_off[b] of `duals`; ranges must not overlap.
  * cost    matrices, FP64 (dtype QAP_FP64) or FP32 (QAP_FP32_CERTIFIED, with
- *         every residual and value rounded toward -inf).  With
- *         QAP_LAP_RESIDUAL each matrix is overwritten by its residual.
+ *         every residual and value rounded toward -inf; QAP_FP32_NEAREST,
+ *         rounded to nearest).  With QAP_LAP_RESIDUAL each matrix is
+ *         overwritten by its residual.
  * value   value[b] receives S, the optimal assignment value reached through
  *         the canonical dual (FP64).
  * duals   nullable; same dtype as cost: [uc | vc | ur | vr], 4 n[b] values:
@@ -248,6 +272,130 @@ qap_status qap_lap_solve(int batch, const int32_t* n, const int64_t* mat_off,
                          const int64_t* vec_off, void* cost, int dtype,
                          double* value, void* duals, int32_t* assign,
                          int flags, void* stream);
+
+/* ---- stop rule, state I/O, snapshots ---------------------------------------- */
+
+/* Stop rule of Algorithm 1 (the loop runs while LB' / UB >= K and LB < UB):
+ * set K and UB for every instance of the handle (UB <= 0 turns the rule off).
+ * Takes effect from the next iteration; an instance that has already stopped
+ * stays stopped. */
+qap_status qap_rlt2_set_stop(qap_rlt2* h, double K, double UB);
+
+/* Per-instance status: active[k] = 1 while instance k's dual ascent runs, 0
+ * once its stop rule has fired; iterations[k] = loop iterations it has run.
+ * Either pointer may be NULL; each holds qap_rlt2_count entries. */
+qap_status qap_rlt2_batch_status(qap_rlt2* h, int* active, int64_t* iterations);
+
+/* Assignment found by the most recent concentration of instance k's B into
+ * LB' (step 7): perm[i] = location of facility i, a permutation of the
+ * instance (its objective is an upper bound on the instance's optimum;
+ * Algorithm 1's UB).  N entries. */
+qap_status qap_rlt2_instance_assignment(qap_rlt2* h, int k, int32_t* perm);
+
+/* Inverse of qap_rlt2_instance_state: overwrite instance k's LB and reduced
+ * costs from host FP64 arrays in the compact layouts above (each pointer
+ * nullable: that part is left as it is).  FP32 modes round each entry once
+ * (toward -inf in QAP_FP32_CERTIFIED, to nearest in QAP_FP32_NEAREST).  With
+ * one stored block per complementary pair, block D_ijkn with i < k is read and
+ * its complement's values are ignored.  A level-1 handle ignores D. */
+qap_status qap_rlt2_load_state(qap_rlt2* h, int k, const double* lb, const double* B, const double* C,
+                               const double* D);
+
+/* Snapshot of the whole handle (every instance's LB, B, C, D, stop flags,
+ * iteration counts, traces and tuned kernel choices) into host memory, for
+ * checkpointing a long run (Section 7).  *size receives the bytes needed;
+ * with buf NULL or capacity < *size nothing else is written (and QAP_OK is
+ * returned when buf is NULL, QAP_EINVAL otherwise). */
+qap_status qap_rlt2_snapshot(qap_rlt2* h, void* buf, uint64_t capacity, uint64_t* size);
+
+/* Restore a snapshot into a handle created with the same instances and
+ * options (QAP_EINVAL if the sizes, precision, level or storage differ).
+ * Iterations after the restore produce the same bits as iterations of the
+ * handle the snapshot was taken from. */
+qap_status qap_rlt2_restore(qap_rlt2* h, const void* buf, uint64_t size);
+
+/* ---- branch and bound (Section 6) --------------------------------------------- */
+
+/* Children of instance k of handle h: child c fixes facility fac[c] at
+ * location loc[c] (indices of instance k, which must be free: 0..N-1).  The
+ * new handle holds `count` instances of size N-1 whose facilities and
+ * locations are instance k's others in ascending order, and whose dual state
+ * is inherited from instance k's current reduced costs:
+ *   LB' = LB + b_ab,  b'_ij = b_ij + c_ijab + c_abij,
+ *   c'_ijkn = c_ijkn + d_abijkn + d_ijabkn + d_ijknab,  d' = d restricted,
+ * a valid dual of the child at least as strong as the parent's LB.  level 2
+ * keeps D; level 1 makes level-1 children (no D; the terms above move into
+ * C all the same).  Options are instance k's handle's (stop rule included).
+ * Call between iterations (not inside a qap_rlt2_step sequence).  Needs
+ * N - 1 >= 3. */
+qap_status qap_rlt2_children(qap_rlt2* h, int k, int count, const int32_t* fac, const int32_t* loc, int level,
+                             qap_rlt2** out);
+
+/* Strong branching of Section 6 at instance k: every child (a -> b) of the
+ * instance is evaluated with the level-1 dual ascent (inherited from the
+ * instance's reduced costs, `iters` level-1 iterations), bounds[a*N + b]
+ * receives its bound (the certified bound in FP32 modes).  The chosen branch
+ * is the facility (kind 0, row a) or location (kind 1, column b) whose
+ * children's smallest bound is the largest, i.e. the branch that raises the
+ * node's bound the most; ties go to the larger sum of bounds, then rows
+ * before columns, then the lower index.  kind, index and bounds nullable. */
+qap_status qap_rlt2_strong_branch(qap_rlt2* h, int k, int iters, double* bounds, int* kind, int* index);
+
+/* QAP objective of permutation perm (perm[i] = location of facility i) with
+ * linear costs B0 (nullable) and a constant: sum_{i,k} f_ik d_perm(i)perm(k)
+ * + sum_i B0[i][perm(i)] + constant.  Host FP64. */
+qap_status qap_objective(int N, const double* F, const double* D, const double* B0, double constant,
+                         const int32_t* perm, double* value);
+
+/* Upper-bound heuristic of Algorithm 1 (UB): pairwise-exchange descent from
+ * perm (in: a permutation, out: a local optimum where no exchange of two
+ * facilities' locations lowers the objective); *value its objective.  Host. */
+qap_status qap_ub_local_search(int N, const double* F, const double* D, const double* B0, double constant,
+                               int32_t* perm, double* value);
+
+typedef struct {
+    int precision;          /* qap_precision of every node's dual ascent          */
+    int device;             /* HIP device; -1 = current                           */
+    void* stream;           /* hipStream_t or NULL                                */
+    int root_iters;         /* dual-ascent iterations at the root                 */
+    int iters;              /* dual-ascent iterations at every other node         */
+    double K;               /* progress limit of the stop rule (0: none)          */
+    double UB;              /* initial upper bound; <= 0: from the heuristic      */
+    int strong_iters;       /* level-1 iterations of the strong-branching
+                               evaluation; < 0: no strong branching (branch on
+                               the lowest free facility)                          */
+    int leaf_size;          /* nodes with at most this many free facilities are
+                               enumerated on the host (3..9)                       */
+    int64_t max_nodes;      /* stop after this many dual-ascent nodes (0: none)  */
+    const char* checkpoint; /* nullable: checkpoint file (written atomically)     */
+    int64_t checkpoint_every; /* dual-ascent nodes between checkpoints (>= 1)     */
+    int resume;             /* 1: continue the run saved in `checkpoint`          */
+} qap_bnb_params;
+
+typedef struct {
+    double value;                 /* best objective found                        */
+    int32_t perm[QAP_RLT2_MAX_N]; /* its permutation (facility -> location)       */
+    double root_bound;            /* bound of the root node                       */
+    int64_t nodes;                /* nodes whose dual ascent ran (resumed runs
+                                     included)                                    */
+    int64_t pruned;               /* nodes discarded by their bound               */
+    int64_t leaves;               /* nodes enumerated on the host                 */
+    int complete;                 /* 1: the tree is exhausted, value is optimal   */
+} qap_bnb_result;
+
+qap_status qap_bnb_default_params(qap_bnb_params* p);
+
+/* Branch and bound of Section 6 on one GPU: a depth-first search whose every
+ * node runs the level-2 dual ascent (this library's), with the children of a
+ * node created together in one batch handle that inherits the node's reduced
+ * costs (qap_rlt2_children), strong branching (qap_rlt2_strong_branch), the
+ * stop rule against the incumbent, incumbents from the heuristic and from the
+ * B-level assignments of every node, and checkpoints of the open nodes (their
+ * fixed assignments) with the incumbent and counters.  Resumed nodes restart
+ * their dual ascent from their subproblem.  Host arrays F and D (N x N),
+ * 3 <= N <= QAP_RLT2_MAX_N. */
+qap_status qap_bnb_solve(int N, const double* F, const double* D, const qap_bnb_params* p,
+                         qap_bnb_result* result);
 
 /* Thread-local description of the most recent failure ("" if none). */
 const char* qap_last_error(void);

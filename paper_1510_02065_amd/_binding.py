@@ -13,7 +13,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqap_rlt2.so")
 
 QAP_OK, QAP_EINVAL, QAP_ENOMEM, QAP_EDEVICE, QAP_ESTATE = 0, -1, -2, -3, -4
-QAP_FP64, QAP_FP32_CERTIFIED = 0, 1
+QAP_FP64, QAP_FP32_CERTIFIED, QAP_FP32_NEAREST = 0, 1, 2
+# Precision names of the Python API: "fp32" is the certified mode (every
+# write rounded toward -inf), "fp32n" the round-to-nearest mode.
+PRECISIONS = {"fp64": QAP_FP64, "fp32": QAP_FP32_CERTIFIED, "fp32n": QAP_FP32_NEAREST}
 QAP_LAP_DEVICE, QAP_LAP_RESIDUAL = 1, 2
 MAX_N = 64
 
@@ -27,7 +30,22 @@ _vp = ctypes.c_void_p
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("trace_level", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("tune_cache", ctypes.c_char_p), ("complementary", ctypes.c_int)]
+                ("tune_cache", ctypes.c_char_p), ("complementary", ctypes.c_int), ("K", ctypes.c_double),
+                ("UB", ctypes.c_double), ("level", ctypes.c_int)]
+
+
+class BnbParams(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("root_iters", ctypes.c_int), ("iters", ctypes.c_int), ("K", ctypes.c_double),
+                ("UB", ctypes.c_double), ("strong_iters", ctypes.c_int), ("leaf_size", ctypes.c_int),
+                ("max_nodes", ctypes.c_int64), ("checkpoint", ctypes.c_char_p),
+                ("checkpoint_every", ctypes.c_int64), ("resume", ctypes.c_int)]
+
+
+class BnbResult(ctypes.Structure):
+    _fields_ = [("value", ctypes.c_double), ("perm", ctypes.c_int32 * MAX_N), ("root_bound", ctypes.c_double),
+                ("nodes", ctypes.c_int64), ("pruned", ctypes.c_int64), ("leaves", ctypes.c_int64),
+                ("complete", ctypes.c_int)]
 
 
 SIGNATURES = {
@@ -54,6 +72,21 @@ SIGNATURES = {
     "qap_rlt2_instance_lap_values": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp, _dp]),
     "qap_rlt2_instance_state": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp, _dp, _dp]),
     "qap_subproblem": (ctypes.c_int, [ctypes.c_int, _dp, _dp, ctypes.c_int, _vp, _vp, _dp, _dp, _dp, _dp]),
+    "qap_rlt2_set_stop": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
+    "qap_rlt2_batch_status": (ctypes.c_int, [_vp, _vp, _vp]),
+    "qap_rlt2_instance_assignment": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
+    "qap_rlt2_load_state": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp, _dp, _dp]),
+    "qap_rlt2_snapshot": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
+    "qap_rlt2_restore": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64]),
+    "qap_rlt2_children": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int,
+                                         ctypes.POINTER(_vp)]),
+    "qap_rlt2_strong_branch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_int)]),
+    "qap_objective": (ctypes.c_int, [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _vp, _dp]),
+    "qap_ub_local_search": (ctypes.c_int, [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _vp, _dp]),
+    "qap_bnb_default_params": (ctypes.c_int, [ctypes.POINTER(BnbParams)]),
+    "qap_bnb_solve": (ctypes.c_int, [ctypes.c_int, _dp, _dp, ctypes.POINTER(BnbParams),
+                                     ctypes.POINTER(BnbResult)]),
 }
 
 _lib = None
@@ -104,10 +137,13 @@ def _dptr(a):
 
 
 def _opts(precision, trace_level, use_graph, device, stream, autotune=True, tune_cache=None,
-          complementary=True):
+          complementary=True, K=0.0, UB=0.0, level=2):
     opts = Opts()
     _check(lib().qap_rlt2_default_opts(ctypes.byref(opts)), "qap_rlt2_default_opts")
-    opts.precision = {"fp64": QAP_FP64, "fp32": QAP_FP32_CERTIFIED}[precision]
+    opts.precision = PRECISIONS[precision]
+    opts.K = float(K)
+    opts.UB = float(UB)
+    opts.level = int(level)
     opts.device = device
     opts.stream = stream
     opts.trace_level = trace_level
@@ -125,7 +161,7 @@ class Rlt2:
 
     def __init__(self, F, D, B0=None, constant=0.0, precision="fp64", trace_level=1,
                  use_graph=True, device=-1, stream=None, autotune=True, tune_cache=None,
-                 complementary=True):
+                 complementary=True, K=0.0, UB=0.0, level=2):
         L = lib()
         F = _f64(F)
         D = _f64(D)
@@ -133,7 +169,8 @@ class Rlt2:
         if F.shape != (N, N) or D.shape != (N, N):
             raise ValueError("F and D must be square and of the same size")
         B0 = None if B0 is None else _f64(B0)
-        opts = _opts(precision, trace_level, use_graph, device, stream, autotune, tune_cache, complementary)
+        opts = _opts(precision, trace_level, use_graph, device, stream, autotune, tune_cache, complementary,
+                     K, UB, level)
         h = _vp()
         _check(L.qap_rlt2_create_ex(N, _dptr(F), _dptr(D), _dptr(B0), float(constant),
                                     ctypes.byref(opts), ctypes.byref(h)), "qap_rlt2_create_ex")
@@ -145,7 +182,7 @@ class Rlt2:
     @classmethod
     def batch(cls, Fs, Ds, B0s=None, constants=None, precision="fp64", trace_level=1,
               use_graph=True, device=-1, stream=None, autotune=True, tune_cache=None,
-              complementary=True):
+              complementary=True, K=0.0, UB=0.0, level=2):
         """Many instances (e.g. branch-and-bound nodes) in one handle."""
         K = len(Fs)
         Fs = [_f64(F) for F in Fs]
@@ -156,7 +193,8 @@ class Rlt2:
         fp = (ctypes.c_void_p * K)(*[F.ctypes.data for F in Fs])
         dp = (ctypes.c_void_p * K)(*[D.ctypes.data for D in Ds])
         bp = (ctypes.c_void_p * K)(*[None if B is None else B.ctypes.data for B in B0s])
-        opts = _opts(precision, trace_level, use_graph, device, stream, autotune, tune_cache, complementary)
+        opts = _opts(precision, trace_level, use_graph, device, stream, autotune, tune_cache, complementary,
+                     K, UB, level)
         h = _vp()
         _check(lib().qap_rlt2_batch_create(K, Ns.ctypes.data, ctypes.cast(fp, _vp), ctypes.cast(dp, _vp),
                                            ctypes.cast(bp, _vp), consts.ctypes.data, ctypes.byref(opts),
@@ -168,6 +206,71 @@ class Rlt2:
         self.precision = precision
         self._keep = (Fs, Ds, B0s)
         return self
+
+    @classmethod
+    def _wrap(cls, h, Ns, precision):
+        self = cls.__new__(cls)
+        self._h = h
+        self.N = int(Ns[0])
+        self.Ns = [int(n) for n in Ns]
+        self.precision = precision
+        return self
+
+    def children(self, k, fac, loc, level=2):
+        """Children of instance k (qap_rlt2_children): child c fixes facility
+        fac[c] at location loc[c] (instance k's indices), inheriting its
+        reduced costs."""
+        fac = np.ascontiguousarray(fac, dtype=np.int32)
+        loc = np.ascontiguousarray(loc, dtype=np.int32)
+        h = _vp()
+        _check(lib().qap_rlt2_children(self._h, int(k), len(fac), fac.ctypes.data, loc.ctypes.data, int(level),
+                                       ctypes.byref(h)), "qap_rlt2_children")
+        return Rlt2._wrap(h, [self.Ns[k] - 1] * len(fac), self.precision)
+
+    def strong_branch(self, k=0, iters=2):
+        """Strong branching at instance k: (kind, index, bounds N x N)."""
+        N = self.Ns[k]
+        bounds = np.empty(N * N)
+        kind = ctypes.c_int()
+        index = ctypes.c_int()
+        _check(lib().qap_rlt2_strong_branch(self._h, int(k), int(iters), _dptr(bounds), ctypes.byref(kind),
+                                            ctypes.byref(index)), "qap_rlt2_strong_branch")
+        return kind.value, index.value, bounds.reshape(N, N)
+
+    def set_stop(self, K, UB):
+        _check(lib().qap_rlt2_set_stop(self._h, float(K), float(UB)), "qap_rlt2_set_stop")
+
+    def status(self):
+        """(active flags, loop iterations run) per instance."""
+        K = len(self.Ns)
+        act = np.empty(K, dtype=np.int32)
+        its = np.empty(K, dtype=np.int64)
+        _check(lib().qap_rlt2_batch_status(self._h, act.ctypes.data, its.ctypes.data), "qap_rlt2_batch_status")
+        return act, its
+
+    def assignment(self, k=0):
+        perm = np.empty(self.Ns[k], dtype=np.int32)
+        _check(lib().qap_rlt2_instance_assignment(self._h, int(k), perm.ctypes.data),
+               "qap_rlt2_instance_assignment")
+        return perm
+
+    def load_state(self, k=0, lb=None, B=None, C=None, D=None):
+        lbv = None if lb is None else np.array([float(lb)])
+        args = [None if a is None else _f64(a).ravel() for a in (B, C, D)]
+        _check(lib().qap_rlt2_load_state(self._h, int(k), _dptr(lbv), *[_dptr(a) for a in args]),
+               "qap_rlt2_load_state")
+
+    def snapshot(self):
+        """The handle's snapshot as bytes (qap_rlt2_snapshot)."""
+        size = ctypes.c_uint64()
+        _check(lib().qap_rlt2_snapshot(self._h, None, 0, ctypes.byref(size)), "qap_rlt2_snapshot")
+        buf = ctypes.create_string_buffer(size.value)
+        _check(lib().qap_rlt2_snapshot(self._h, buf, size.value, ctypes.byref(size)), "qap_rlt2_snapshot")
+        return buf.raw[: size.value]
+
+    def restore(self, data):
+        buf = ctypes.create_string_buffer(bytes(data), len(data))
+        _check(lib().qap_rlt2_restore(self._h, buf, len(data)), "qap_rlt2_restore")
 
     def count(self):
         c = ctypes.c_int()
@@ -274,6 +377,52 @@ class Rlt2:
         return float(lb[0]), B, C, D
 
 
+def objective(F, D, perm, B0=None, constant=0.0):
+    """QAP objective of perm (qap_objective)."""
+    F = _f64(F)
+    D = _f64(D)
+    perm = np.ascontiguousarray(perm, dtype=np.int32)
+    B0 = None if B0 is None else _f64(B0)
+    out = ctypes.c_double()
+    _check(lib().qap_objective(F.shape[0], _dptr(F), _dptr(D), _dptr(B0), float(constant), perm.ctypes.data,
+                               ctypes.byref(out)), "qap_objective")
+    return out.value
+
+
+def local_search(F, D, perm, B0=None, constant=0.0):
+    """Pairwise-exchange descent from perm (qap_ub_local_search): (perm, value)."""
+    F = _f64(F)
+    D = _f64(D)
+    p = np.array(perm, dtype=np.int32)
+    B0 = None if B0 is None else _f64(B0)
+    out = ctypes.c_double()
+    _check(lib().qap_ub_local_search(F.shape[0], _dptr(F), _dptr(D), _dptr(B0), float(constant), p.ctypes.data,
+                                     ctypes.byref(out)), "qap_ub_local_search")
+    return p, out.value
+
+
+def bnb_solve(F, D, **kw):
+    """Branch and bound (qap_bnb_solve).  Keyword arguments set the fields of
+    qap_bnb_params (precision as a name); returns a dict of the result."""
+    F = _f64(F)
+    D = _f64(D)
+    N = F.shape[0]
+    prm = BnbParams()
+    _check(lib().qap_bnb_default_params(ctypes.byref(prm)), "qap_bnb_default_params")
+    for key, val in kw.items():
+        if key == "precision":
+            val = PRECISIONS[val]
+        elif key == "checkpoint":
+            val = None if val is None else str(val).encode()
+        elif key == "stream":
+            val = None if val is None else int(val)
+        setattr(prm, key, val)
+    res = BnbResult()
+    _check(lib().qap_bnb_solve(N, _dptr(F), _dptr(D), ctypes.byref(prm), ctypes.byref(res)), "qap_bnb_solve")
+    return {"value": res.value, "perm": np.array(res.perm[:N], dtype=np.int32), "root_bound": res.root_bound,
+            "nodes": res.nodes, "pruned": res.pruned, "leaves": res.leaves, "complete": bool(res.complete)}
+
+
 def subproblem(F, D, fac, loc):
     """Branch-and-bound node: fix facility fac[t] at location loc[t].
     Returns (Fsub, Dsub, B0sub, constant) (qap_subproblem)."""
@@ -331,12 +480,13 @@ def lap_solve(mats, residual=False, want_duals=True, want_assign=True):
 
 
 def lap_solve_device(n, mat_off, vec_off, cost, value, duals=None, assign=None, residual=False,
-                     stream=None, fp32=False):
+                     stream=None, fp32=False, nearest=False):
     """Device-pointer batch: every argument is a torch CUDA tensor (or None);
     the call is asynchronous on `stream` (a torch.cuda.Stream or None)."""
     ptr = (lambda t: None if t is None else t.data_ptr())
     flags = QAP_LAP_DEVICE | (QAP_LAP_RESIDUAL if residual else 0)
     sp = None if stream is None else stream.cuda_stream
     _check(lib().qap_lap_solve(int(n.numel()), ptr(n), ptr(mat_off), ptr(vec_off), ptr(cost),
-                               QAP_FP32_CERTIFIED if fp32 else QAP_FP64, ptr(value), ptr(duals),
+                               (QAP_FP32_NEAREST if nearest else QAP_FP32_CERTIFIED) if fp32 else QAP_FP64,
+                               ptr(value), ptr(duals),
                                ptr(assign), flags, sp), "qap_lap_solve")

@@ -73,23 +73,27 @@ __device__ __forceinline__ void stage_block(T* __restrict__ M, const T* __restri
 // problems per wave, one wave per workgroup.  parent += S, the block is
 // replaced by its residual, values[...] = S when values is not null (values
 // are packed like the parents).  `mode` applies to the D family only.
-template <typename T, int SEG, int K, int FAM>
-__global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __restrict__ C, T* __restrict__ B,
-                                                     const Inst* __restrict__ inst, FamilyClass fc, int nmax,
-                                                     double* __restrict__ values, int mode)
+template <int PM, int SEG, int K, int FAM>
+__global__ __launch_bounds__(64) void k_lap_family_s(StoreT<PM>* __restrict__ D, StoreT<PM>* __restrict__ C,
+                                                     StoreT<PM>* __restrict__ B, const Inst* __restrict__ inst,
+                                                     FamilyClass fc, int nmax, double* __restrict__ values, int mode,
+                                                     const int* __restrict__ act)
 {
+    using T = StoreT<PM>;
+    constexpr bool DOWN = PM == kPrecF32Down;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int LPW = 64 / SEG;
     const int seg = threadIdx.x / SEG;
     const int lane = threadIdx.x & (SEG - 1);
     const long long x = (long long)blockIdx.x * LPW + seg;
-    const bool active = x < fc.total;
+    int kk = 0;
+    if (x < fc.total) kk = find_seg(fc.pre, fc.Kc, x);
+    const bool active = x < fc.total && act[fc.cls[kk]];
     int n = 0;
     T* blk = nullptr;
     long long ld = 0;   // row stride of the block in global memory
     long long pidx = 0, pidx2 = -1;
     if (active) {
-        const int kk = find_seg(fc.pre, fc.Kc, x);
         const Inst I = inst[fc.cls[kk]];
         const long long b = x - fc.pre[kk];
         if (FAM == kFamD) {
@@ -118,18 +122,13 @@ __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __res
     wave_sync();
     double S;
     if constexpr (K == 1)
-        S = lap_concentrate_flat<T, SEG>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
+        S = lap_concentrate_flat<T, SEG, DOWN>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
     else
-        S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
+        S = lap_concentrate_slots<T, SEG, K, DOWN>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
     if (active && lane == 0) {
         T* parent = (FAM == kFamD) ? C : B;
-        if constexpr (sizeof(T) == 8) {
-            parent[pidx] = parent[pidx] + S;
-            if (pidx2 >= 0) parent[pidx2] = parent[pidx2] + S;
-        } else {
-            parent[pidx] = to_float_down(add_down((double)parent[pidx], S));
-            if (pidx2 >= 0) parent[pidx2] = to_float_down(add_down((double)parent[pidx2], S));
-        }
+        parent[pidx] = store_add<PM>(parent[pidx], S);
+        if (pidx2 >= 0) parent[pidx2] = store_add<PM>(parent[pidx2], S);
         if (values) {
             values[pidx] = S;
             if (pidx2 >= 0) values[pidx2] = S;
@@ -140,76 +139,94 @@ __global__ __launch_bounds__(64) void k_lap_family_s(T* __restrict__ D, T* __res
 // B -> LB' and LB += LB' (steps 7-8), one problem of size N per instance of
 // the class, K columns per lane.  lb[2k] = LB, lb[2k+1] = LB' (FP64; in FP32
 // certified mode the bound accumulates rounding toward -inf).  The instance's
-// trace gets (LB, LB') at position counter[k]++ when below trace_cap.
-template <typename T, int SEG, int K>
-__global__ __launch_bounds__(64) void k_lap_B_s(T* __restrict__ B, const Inst* __restrict__ inst, FamilyClass fc,
-                                                int nmax, double* __restrict__ lb, double* __restrict__ trace,
-                                                long long* __restrict__ counter, long long trace_cap,
-                                                double* __restrict__ values)
+// trace gets (LB, LB') at position counter[k]++ when below trace_cap, and
+// sigma (nullable, packed like B) the assignment of the B problem, a
+// permutation of the instance.  Stop rule of Algorithm 1, with stop[0] = K and
+// stop[1] = UB (UB <= 0: none): the instance's act flag is cleared once
+// LB >= UB or LB' / UB < K.
+template <int PM, int SEG, int K>
+__global__ __launch_bounds__(64) void k_lap_B_s(StoreT<PM>* __restrict__ B, const Inst* __restrict__ inst,
+                                                FamilyClass fc, int nmax, double* __restrict__ lb,
+                                                double* __restrict__ trace, long long* __restrict__ counter,
+                                                long long trace_cap, double* __restrict__ values,
+                                                int32_t* __restrict__ sigma, int* __restrict__ act,
+                                                const double* __restrict__ stop)
 {
+    using T = StoreT<PM>;
+    constexpr bool DOWN = PM == kPrecF32Down;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int LPW = 64 / SEG;
     const int seg = threadIdx.x / SEG;
     const int lane = threadIdx.x & (SEG - 1);
     const long long x = (long long)blockIdx.x * LPW + seg;
-    const bool active = x < fc.total;
-    const int k = active ? fc.cls[x] : 0;
+    const int k = x < fc.total ? fc.cls[x] : 0;
+    const bool active = x < fc.total && act[k];
     const Inst I = inst[k];
     const int n = active ? I.N : 0;
     T* blk = B + I.offB;
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
     stage_block<T, SEG, K>(sc.M, blk, n, n, lane);
     wave_sync();
+    int32_t* sg = (active && sigma) ? sigma + I.offB : nullptr;
     double S;
     if constexpr (K == 1)
-        S = lap_concentrate_flat<T, SEG>(sc, n, active ? blk : nullptr, n, nullptr, nullptr);
+        S = lap_concentrate_flat<T, SEG, DOWN>(sc, n, active ? blk : nullptr, n, nullptr, sg);
     else
-        S = lap_concentrate_slots<T, SEG, K>(sc, n, active ? blk : nullptr, n, nullptr, nullptr);
+        S = lap_concentrate_slots<T, SEG, K, DOWN>(sc, n, active ? blk : nullptr, n, nullptr, sg);
     if (active && lane == 0) {
-        const double L = (sizeof(T) == 4) ? add_down(lb[2 * k], S) : lb[2 * k] + S;
+        const double L = DOWN ? add_down(lb[2 * k], S) : lb[2 * k] + S;
         lb[2 * k] = L;
         lb[2 * k + 1] = S;
         if (values) values[k] = S;
         if (counter) {
             const long long t = counter[k];
-            if (t < trace_cap) {
+            if (trace && t < trace_cap) {
                 trace[(k * trace_cap + t) * 2] = L;
                 trace[(k * trace_cap + t) * 2 + 1] = S;
             }
             counter[k] = t + 1;
         }
+        const double Kp = stop[0], UB = stop[1];
+        if (UB > 0.0 && (L >= UB || S < Kp * UB)) act[k] = 0;
     }
 }
 
-// Generic batch (qap_lap_solve): problem b has size n[b] (<= SEG, else its
-// value is NaN and nothing else is written), matrix at cost + mat_off[b],
-// vectors at vec_off[b].
-template <typename T, int SEG>
-__global__ __launch_bounds__(64) void k_lap_batch(int batch, const int32_t* __restrict__ nv,
+// Generic batch (qap_lap_solve): launch slot s < count solves problem
+// b = idx[s] (b = s when idx is null); count = *dcount when dcount is not
+// null, else `count`.  Problem b has size n[b] (<= SEG, else its value is NaN
+// and nothing else is written), matrix at cost + mat_off[b], vectors at
+// vec_off[b] (vec_off may be null when duals and assign are).
+template <int PM, int SEG>
+__global__ __launch_bounds__(64) void k_lap_batch(int count, const int* __restrict__ dcount,
+                                                  const int32_t* __restrict__ idx, const int32_t* __restrict__ nv,
                                                   const int64_t* __restrict__ mat_off,
                                                   const int64_t* __restrict__ vec_off,
-                                                  T* __restrict__ cost, double* __restrict__ value,
-                                                  T* __restrict__ duals, int32_t* __restrict__ assign,
+                                                  StoreT<PM>* __restrict__ cost, double* __restrict__ value,
+                                                  StoreT<PM>* __restrict__ duals, int32_t* __restrict__ assign,
                                                   int write_residual)
 {
+    using T = StoreT<PM>;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int LPW = 64 / SEG;
     const int seg = threadIdx.x / SEG;
     const int lane = threadIdx.x & (SEG - 1);
-    const int64_t b = (int64_t)blockIdx.x * LPW + seg;
-    int n = (b < batch) ? nv[b] : 0;
+    const int cnt = dcount ? *dcount : count;
+    const int64_t s = (int64_t)blockIdx.x * LPW + seg;
+    const bool in = s < cnt;
+    const int64_t b = in ? (idx ? (int64_t)idx[s] : s) : 0;
+    int n = in ? nv[b] : 0;
     const bool bad = n < 0 || n > SEG;
     if (bad) n = 0;
     const SlotScratch<T, SEG, 1> sc(smem + seg * SlotLds<T, SEG, 1>::bytes(SEG), n);
-    T* mat = (b < batch && !bad) ? cost + mat_off[b] : nullptr;
-    const int64_t vo = (b < batch && !bad) ? vec_off[b] : 0;
+    T* mat = (in && !bad) ? cost + mat_off[b] : nullptr;
+    const int64_t vo = (in && !bad && vec_off) ? vec_off[b] : 0;
     stage_block<T, SEG, 1>(sc.M, mat, n, n, lane);
     wave_sync();
-    const double S = lap_concentrate_flat<T, SEG>(sc, n, (write_residual && n > 0) ? mat : nullptr, n,
-                                                  (duals && n > 0) ? duals + 4 * vo : nullptr,
-                                                  (assign && n > 0) ? assign + vo : nullptr);
+    const double S = lap_concentrate_flat<T, SEG, PM == kPrecF32Down>(
+        sc, n, (write_residual && n > 0) ? mat : nullptr, n, (duals && n > 0) ? duals + 4 * vo : nullptr,
+        (assign && n > 0) ? assign + vo : nullptr);
     // A quiet NaN written by bit pattern marks a problem that was not solved.
-    if (b < batch && lane == 0) value[b] = bad ? __longlong_as_double(0x7ff8000000000000ll) : S;
+    if (in && lane == 0) value[b] = bad ? __longlong_as_double(0x7ff8000000000000ll) : S;
 }
 
 }  // namespace qap

@@ -31,9 +31,10 @@
 // of shortest distances in the column graph whose arc c -> q costs the reduced
 // cost M[sigma^-1(c)][q] - u - v >= 0, starting from label -v_q at every
 // column: one dense Dijkstra pass.  The row point is the same on the row graph.
-// In FP64 both residual halves are >= 0 exactly, because the subtracted dual
-// is a row (column) minimum of the already rounded differences.  The FP32
-// certified variant is described at its code.
+// With round-to-nearest arithmetic (FP64, or FP32 nearest) both residual
+// halves are >= 0 exactly, because the subtracted dual is a row (column)
+// minimum of the already rounded differences.  The FP32 certified variant is
+// described at its code.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -164,7 +165,7 @@ struct SlotScratch {
     }
 };
 
-template <typename T, int SEG, int K>
+template <typename T, int SEG, int K, bool DOWN>
 __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc, int n, T* __restrict__ R,
                                                long long ldr, T* __restrict__ duals, int32_t* __restrict__ assign,
                                                const T (&vc)[K], const T (&ur)[K], const int (&sg)[K]);
@@ -173,7 +174,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
 // v (column duals) and p (row matched to each column) of this lane's K
 // columns, ucol the dual of that row; the LDS copies sc.p (row indices) and
 // sc.u (row dual per column) hold the same for every column.
-template <typename T, int SEG, int K>
+template <typename T, int SEG, int K, bool DOWN>
 __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG, K>& sc, int n,
                                                        T* __restrict__ R, long long ldr, T* __restrict__ duals,
                                                        int32_t* __restrict__ assign, const T (&v)[K],
@@ -276,14 +277,17 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
         vc[s] = v[s] + x[s];     // lane as columns
         ur[s] = urow[s] + y[s];  // lane as rows
     }
-    return lap_complete<T, SEG, K>(sc, n, R, ldr, duals, assign, vc, ur, sg);
+    return lap_complete<T, SEG, K, DOWN>(sc, n, R, ldr, duals, assign, vc, ur, sg);
 }
 
 // From the canonical points to the residual and S: vc (this lane's columns'
 // column-canonical duals), ur (its rows' row-canonical duals) and sg (sigma of
 // its rows, for `assign`).  The other halves of the two points are completed
 // here: u^c_r = min_q (M_rq - v^c_q), v^r_q = min_r (M_rq - u^r_r).
-template <typename T, int SEG, int K>
+// DOWN selects the FP32 certified completion (every written value rounded
+// toward -inf); otherwise the completion runs in T with round-to-nearest and
+// S is summed in FP64.
+template <typename T, int SEG, int K, bool DOWN>
 __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc, int n, T* __restrict__ R,
                                                long long ldr, T* __restrict__ duals, int32_t* __restrict__ assign,
                                                const T (&vc)[K], const T (&ur)[K], const int (&sg)[K])
@@ -300,8 +304,9 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
     }
     wave_sync();
 
-    if constexpr (sizeof(T) == 8) {
-        // ---- FP64: residual = mean of the residuals under the two points ----
+    if constexpr (!DOWN) {
+        // ---- round to nearest: residual = mean of the residuals under the
+        // two points ----
         for (int s = 0; s < K; ++s) {
             if (!ok[s]) continue;
             sc.u[c[s]] = vc[s];
@@ -333,12 +338,12 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
                 }
             }
         }
-        T xuc[K], xvc[K], xur[K], xvr[K];
+        double xuc[K], xvc[K], xur[K], xvr[K];
         for (int s = 0; s < K; ++s) {
-            xuc[s] = ok[s] ? uc[s] : (T)0;
-            xvc[s] = ok[s] ? vc[s] : (T)0;
-            xur[s] = ok[s] ? ur[s] : (T)0;
-            xvr[s] = ok[s] ? vr[s] : (T)0;
+            xuc[s] = ok[s] ? (double)uc[s] : 0.0;
+            xvc[s] = ok[s] ? (double)vc[s] : 0.0;
+            xur[s] = ok[s] ? (double)ur[s] : 0.0;
+            xvr[s] = ok[s] ? (double)vr[s] : 0.0;
             if (!ok[s]) continue;
             if (duals != nullptr) {
                 duals[c[s]] = uc[s];
@@ -348,11 +353,11 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             }
             if (assign != nullptr) assign[c[s]] = sg[s];
         }
-        auto plus = [](T a, T b) { return a + b; };
-        const T suc = tree_sum64<SEG, K>(xuc, plus);
-        const T svc = tree_sum64<SEG, K>(xvc, plus);
-        const T sur = tree_sum64<SEG, K>(xur, plus);
-        const T svr = tree_sum64<SEG, K>(xvr, plus);
+        auto plus = [](double a, double b) { return a + b; };
+        const double suc = tree_sum64<SEG, K>(xuc, plus);
+        const double svc = tree_sum64<SEG, K>(xvc, plus);
+        const double sur = tree_sum64<SEG, K>(xur, plus);
+        const double svr = tree_sum64<SEG, K>(xvr, plus);
         wave_sync();
         return 0.5 * ((suc + svc) + (sur + svr));
     } else {
@@ -554,7 +559,7 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
 // solver's assignment.
 // Returns S to every lane of the segment.  Called by whole waves; segments may
 // have different n (0 <= n <= SEG*K).
-template <typename T, int SEG, int K>
+template <typename T, int SEG, int K, bool DOWN>
 __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG, K>& sc, int n,
                                                         T* __restrict__ R, long long ldr, T* __restrict__ duals,
                                                         int32_t* __restrict__ assign)
@@ -681,7 +686,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
         wave_sync();
     }
 
-    return lap_canonical_finish<T, SEG, K>(sc, n, R, ldr, duals, assign, v, p, ucol);
+    return lap_canonical_finish<T, SEG, K, DOWN>(sc, n, R, ldr, duals, assign, v, p, ucol);
 }
 
 // Lane bits of a predicate over this lane's segment (bit 0 = the segment's
@@ -795,7 +800,7 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
 // such lane is the lowest column), and the matched rows are kept in LDS as row
 // offsets r * n.  The decisions and the arithmetic are those of
 // lap_concentrate_slots.
-template <typename T, int SEG>
+template <typename T, int SEG, bool DOWN>
 __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG, 1>& sc, int n,
                                                        T* __restrict__ R, long long ldr, T* __restrict__ duals,
                                                        int32_t* __restrict__ assign)
@@ -925,7 +930,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
         const T vca[1] = {vc};
         const T ura[1] = {ur};
         const int sga[1] = {sg};
-        return lap_complete<T, SEG, 1>(sc, n, R, ldr, duals, assign, vca, ura, sga);
+        return lap_complete<T, SEG, 1, DOWN>(sc, n, R, ldr, duals, assign, vca, ura, sga);
     } else {
         // Row indices for the sequential canonical passes.
         const int prow = poff >= 0 ? poff / n : -1;
@@ -934,7 +939,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
         const T va[1] = {v};
         const int pa[1] = {prow};
         const T ua[1] = {ucol};
-        return lap_canonical_finish<T, SEG, 1>(sc, n, R, ldr, duals, assign, va, pa, ua);
+        return lap_canonical_finish<T, SEG, 1, DOWN>(sc, n, R, ldr, duals, assign, va, pa, ua);
     }
 }
 

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace qap {
 
 __device__ __forceinline__ int skip1(int r, int a) { return r + (r >= a); }
@@ -27,10 +29,15 @@ __device__ __forceinline__ int skip2(int r, int lo, int hi) {
 __device__ __forceinline__ int drop1(int x, int a) { return x - (x > a); }
 __device__ __forceinline__ int drop2(int x, int a, int b) { return x - (x > a) - (x > b); }
 
-// ---- arithmetic of the two precisions ---------------------------------------
+// ---- arithmetic of the three precisions -------------------------------------
 // FP64 mode: plain IEEE round-to-nearest; the element-wise steps perform
 // exactly the operations of the algorithm in the same order as a plain
 // sequential reference, and so match it bit for bit.
+//
+// FP32 nearest mode: reduced costs are stored as floats; every value written
+// into the state is computed in FP64 with the FP64 mode's operations and
+// rounded to nearest once, so the FP32 state follows the FP64 trajectory
+// without a systematic bias.
 //
 // FP32 certified mode: reduced costs are stored as floats, and every value
 // written into the state (B, C, D, LB) is computed in FP64 and rounded
@@ -92,6 +99,37 @@ __device__ __forceinline__ float add_down_to_float(double a, double b) {
     float f = (float)s;
     if ((double)f > s || ((double)f == s && err < 0.0)) f = next_down(f);
     return f;
+}
+
+// Precision modes (the values of qap_precision).  kPrecF64: FP64 state,
+// round-to-nearest.  kPrecF32Down: FP32 state, every value written rounded
+// toward -inf once (the represented objective can only fall, a proof of
+// validity).  kPrecF32Near: FP32 state, every value computed in FP64 and
+// rounded to nearest once (no systematic drift; validity rests on the FP64
+// certification over the stored state).
+enum : int { kPrecF64 = 0, kPrecF32Down = 1, kPrecF32Near = 2 };
+template <int PM>
+using StoreT = typename std::conditional<PM == kPrecF64, double, float>::type;
+
+// An FP64 value as written into the state of mode PM.
+template <int PM>
+__device__ __forceinline__ StoreT<PM> store_val(double x) {
+    if constexpr (PM == kPrecF64)
+        return x;
+    else if constexpr (PM == kPrecF32Down)
+        return to_float_down(x);
+    else
+        return (float)x;
+}
+// parent + S (S in FP64) as written into the state of mode PM.
+template <int PM>
+__device__ __forceinline__ StoreT<PM> store_add(StoreT<PM> parent, double S) {
+    if constexpr (PM == kPrecF64)
+        return parent + S;
+    else if constexpr (PM == kPrecF32Down)
+        return to_float_down(add_down((double)parent, S));
+    else
+        return (float)((double)parent + S);
 }
 
 // Block number of D_{(a,la),(b,lb)} (= position of c_{a la b lb} in C).
@@ -166,7 +204,9 @@ __device__ __forceinline__ int entry_of(int N, int a, int la, int b, int lb, int
 // A handle holds K independent instances (a single QAP, or the nodes of a
 // branch-and-bound batch).  Their B, C and D arrays are packed one after the
 // other; every kernel below covers all instances in one launch and finds its
-// instance by binary search in a prefix array.
+// instance by binary search in a prefix array.  The iteration kernels also take
+// act[], one flag per instance: 1 while its dual ascent runs, 0 once the stop
+// rule of Algorithm 1 has ended it, after which they leave its state as it is.
 struct Inst {
     int N;
     int ntri;          // N(N-1)(N-2)/6 facility triples
@@ -195,23 +235,23 @@ __device__ __forceinline__ int find_seg(const long long* __restrict__ pre, int K
 
 // Initial dual of one instance (the lines of Algorithm 1 before its loop):
 //   b_ij = f_ii d_jj (+ B0_ij), c_ijkn = f_ik d_jn.
-template <typename T>
+template <int PM>
 __global__ __launch_bounds__(256) void k_init(const double* __restrict__ F, const double* __restrict__ Dm,
-                                              const double* __restrict__ B0, T* __restrict__ B,
-                                              T* __restrict__ C, int N)
+                                              const double* __restrict__ B0, StoreT<PM>* __restrict__ B,
+                                              StoreT<PM>* __restrict__ C, int N)
 {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int n1 = N - 1;
     const int64_t nC = (int64_t)N * N * n1 * n1;
     if (x < (int64_t)N * N) {
         const int i = (int)(x / N), j = (int)(x % N);
-        if constexpr (sizeof(T) == 8) {
-            double b = F[i * N + i] * Dm[j * N + j];
-            if (B0) b = b + B0[x];
-            B[x] = b;
-        } else {
+        if constexpr (PM == kPrecF32Down) {
             const double b = mul_down(F[i * N + i], Dm[j * N + j]);
             B[x] = add_down_to_float(b, B0 ? B0[x] : 0.0);
+        } else {
+            double b = F[i * N + i] * Dm[j * N + j];
+            if (B0) b = b + B0[x];
+            B[x] = (StoreT<PM>)b;
         }
     }
     if (x < nC) {
@@ -219,38 +259,82 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ F, cons
         const int rem = (int)(x % (n1 * n1));
         const int i = ij / N, j = ij % N;
         const int k = skip1(rem / n1, i), n = skip1(rem % n1, j);
-        if constexpr (sizeof(T) == 8)
-            C[x] = F[i * N + k] * Dm[j * N + n];
-        else
+        if constexpr (PM == kPrecF32Down)
             C[x] = mul_down_to_float(F[i * N + k], Dm[j * N + n]);
+        else
+            C[x] = (StoreT<PM>)(F[i * N + k] * Dm[j * N + n]);
     }
 }
+
 
 // Steps 1-2 precomputation, one thread per C entry of every instance: the
 // amount each entry of block D_beta receives,
 //   CC_beta = (c_beta + b_ij / (N-1)) / (N-2),
 // after which c is cleared (B is cleared by the sweep, which does not read it).
-template <typename T>
-__global__ __launch_bounds__(256) void k_spread_prep(T* __restrict__ C, const T* __restrict__ B,
-                                                     T* __restrict__ CC, const Inst* __restrict__ inst,
+template <int PM>
+__global__ __launch_bounds__(256) void k_spread_prep(StoreT<PM>* __restrict__ C, const StoreT<PM>* __restrict__ B,
+                                                     StoreT<PM>* __restrict__ CC, const Inst* __restrict__ inst,
                                                      const long long* __restrict__ preC, int K,
-                                                     long long totalC)
+                                                     long long totalC, const int* __restrict__ act)
 {
+    using T = StoreT<PM>;
     const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= totalC) return;
-    const Inst I = inst[find_seg(preC, K, x)];
+    const int kk = find_seg(preC, K, x);
+    if (!act[kk]) return;
+    const Inst I = inst[kk];
     const int N = I.N, n1 = N - 1;
     const int ij = (int)((x - I.offC) / (n1 * n1));
     const T bij = B[I.offB + ij];
-    if constexpr (sizeof(T) == 8) {
-        const T share_b = bij / (T)(N - 1);
-        const T c = C[x] + share_b;
-        CC[x] = c / (T)(N - 2);
-    } else {
+    if constexpr (PM == kPrecF32Down) {
         const double c = add_down((double)C[x], div_down((double)bij, (double)(N - 1)));
         CC[x] = to_float_down(div_down(c, (double)(N - 2)));
+    } else {
+        const double share_b = (double)bij / (double)(N - 1);
+        const double c = (double)C[x] + share_b;
+        CC[x] = (T)(c / (double)(N - 2));
     }
     C[x] = (T)0;
+}
+
+// Step 1 alone (the level-1 dual ascent, which has no D): c += b_ij / (N-1)
+// over every C entry of the active instances.  B is cleared by k_clear_B.
+template <int PM>
+__global__ __launch_bounds__(256) void k_spread_B(StoreT<PM>* __restrict__ C, const StoreT<PM>* __restrict__ B,
+                                                  const Inst* __restrict__ inst, const long long* __restrict__ preC,
+                                                  int K, long long totalC, const int* __restrict__ act)
+{
+    using T = StoreT<PM>;
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= totalC) return;
+    const int kk = find_seg(preC, K, x);
+    if (!act[kk]) return;
+    const Inst I = inst[kk];
+    const int N = I.N, n1 = N - 1;
+    const int ij = (int)((x - I.offC) / (n1 * n1));
+    const T bij = B[I.offB + ij];
+    if constexpr (PM == kPrecF32Down)
+        C[x] = to_float_down(add_down((double)C[x], div_down((double)bij, (double)(N - 1))));
+    else
+        C[x] = (T)((double)C[x] + (double)bij / (double)(N - 1));
+}
+
+// b = 0 over the active instances (after step 1 of the level-1 ascent).
+template <int PM>
+__global__ __launch_bounds__(256) void k_clear_B(StoreT<PM>* __restrict__ B, const long long* __restrict__ preB,
+                                                 int K, long long totalB, const int* __restrict__ act)
+{
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= totalB) return;
+    if (act[find_seg(preB, K, x)]) B[x] = (StoreT<PM>)0;
+}
+
+// The sweep kernels clear instance I's B (N^2 entries) from the workgroup
+// that takes the instance's first facility triple.
+template <typename T>
+__device__ __forceinline__ void clear_inst_B(T* __restrict__ B, const Inst& I, int tid, int nthreads)
+{
+    for (int e = tid; e < I.N * I.N; e += nthreads) B[I.offB + e] = (T)0;
 }
 
 // Steps 1-3 on D: every entry gets its block's spread share, then each group
@@ -271,16 +355,19 @@ __global__ __launch_bounds__(256) void k_spread_prep(T* __restrict__ C, const T*
 // used cache lines of the four strided members meet in its L2.
 // The first totalB threads of the grid also clear B.  Used when every block
 // is stored; see k_sweep_cube for one block per complementary pair.
-template <typename T>
-__global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __restrict__ CC,
-                                               T* __restrict__ B, const int* __restrict__ tri,
+template <int PM>
+__global__ __launch_bounds__(256) void k_sweep(StoreT<PM>* __restrict__ Dd, const StoreT<PM>* __restrict__ CC,
+                                               StoreT<PM>* __restrict__ B, const int* __restrict__ tri,
                                                const Inst* __restrict__ inst,
-                                               const long long* __restrict__ preWG, int K, long long totalB)
+                                               const long long* __restrict__ preWG, int K,
+                                               const int* __restrict__ act)
 {
-    const long long gx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gx < totalB) B[gx] = (T)0;
-    const Inst I = inst[find_seg(preWG, K, (long long)blockIdx.x)];
+    using T = StoreT<PM>;
+    const int kk = find_seg(preWG, K, (long long)blockIdx.x);
+    if (!act[kk]) return;   // whole workgroup
+    const Inst I = inst[kk];
     const int lb = (int)((long long)blockIdx.x - I.wg0);
+    if (lb == 0) clear_inst_B(B, I, threadIdx.x, 256);
     const int xcd = lb & 7;
     const int local = lb >> 3;
     const int t = (local / I.wpt) * 8 + xcd;
@@ -312,20 +399,20 @@ __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __re
     const int64_t a5 = b5 * ldD + entry_of(N, p, q, k, n, i, j);
 
     T mean;
-    if constexpr (sizeof(T) == 8) {
-        const T m0 = Dk[a0] + CCk[b0];
-        const T m1 = Dk[a1] + CCk[b1];
-        const T m2 = Dk[a2] + CCk[b2];
-        const T m3 = Dk[a3] + CCk[b3];
-        const T m4 = Dk[a4] + CCk[b4];
-        const T m5 = Dk[a5] + CCk[b5];
-        T s = m0;
+    if constexpr (PM != kPrecF32Down) {
+        const double m0 = (double)Dk[a0] + (double)CCk[b0];
+        const double m1 = (double)Dk[a1] + (double)CCk[b1];
+        const double m2 = (double)Dk[a2] + (double)CCk[b2];
+        const double m3 = (double)Dk[a3] + (double)CCk[b3];
+        const double m4 = (double)Dk[a4] + (double)CCk[b4];
+        const double m5 = (double)Dk[a5] + (double)CCk[b5];
+        double s = m0;
         s += m1;
         s += m2;
         s += m3;
         s += m4;
         s += m5;
-        mean = s / (T)6;
+        mean = (T)(s / 6.0);
     } else {
         double s = add_down((double)Dk[a0], (double)CCk[b0]);
         s = add_down(s, (double)Dk[a1]);
@@ -370,23 +457,23 @@ __global__ __launch_bounds__(256) void k_sweep(T* __restrict__ Dd, const T* __re
 // large for LDS, N > 58 in FP64) reads the spread shares from global memory.
 constexpr int kSweepParts = 8;
 
-template <typename T>
+template <int PM, typename T = StoreT<PM>>
 __device__ __forceinline__ T six_way_mean(T A0, T B0, T C0, T x0, T x1, T x2, T x3, T x4, T x5)
 {
-    if constexpr (sizeof(T) == 8) {
-        const T m0 = A0 + x0;
-        const T m1 = B0 + x1;
-        const T m2 = A0 + x2;
-        const T m3 = C0 + x3;
-        const T m4 = B0 + x4;
-        const T m5 = C0 + x5;
-        T sum = m0;
+    if constexpr (PM != kPrecF32Down) {
+        const double m0 = (double)A0 + (double)x0;
+        const double m1 = (double)B0 + (double)x1;
+        const double m2 = (double)A0 + (double)x2;
+        const double m3 = (double)C0 + (double)x3;
+        const double m4 = (double)B0 + (double)x4;
+        const double m5 = (double)C0 + (double)x5;
+        double sum = m0;
         sum += m1;
         sum += m2;
         sum += m3;
         sum += m4;
         sum += m5;
-        return sum / (T)6;
+        return (T)(sum / 6.0);
     } else {
         double sum = add_down((double)A0, (double)x0);
         sum = add_down(sum, (double)B0);
@@ -403,19 +490,21 @@ __device__ __forceinline__ T six_way_mean(T A0, T B0, T C0, T x0, T x1, T x2, T 
     }
 }
 
-template <typename T, bool STAGE>
-__global__ __launch_bounds__(256) void k_sweep_cube(T* __restrict__ Dd, const T* __restrict__ CC,
-                                                    T* __restrict__ B, const int* __restrict__ tri,
+template <int PM, bool STAGE>
+__global__ __launch_bounds__(256) void k_sweep_cube(StoreT<PM>* __restrict__ Dd, const StoreT<PM>* __restrict__ CC,
+                                                    StoreT<PM>* __restrict__ B, const int* __restrict__ tri,
                                                     const Inst* __restrict__ inst,
-                                                    const long long* __restrict__ preWG, int K, long long totalB,
-                                                    int Nmax)
+                                                    const long long* __restrict__ preWG, int K, int Nmax,
+                                                    const int* __restrict__ act)
 {
+    using T = StoreT<PM>;
     extern __shared__ __align__(16) unsigned char smem[];
     T* __restrict__ X = reinterpret_cast<T*>(smem);   // [6][Nmax][Nmax]
-    const long long gx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gx < totalB) B[gx] = (T)0;
-    const Inst I = inst[find_seg(preWG, K, (long long)blockIdx.x)];
+    const int kk = find_seg(preWG, K, (long long)blockIdx.x);
+    if (!act[kk]) return;   // whole workgroup
+    const Inst I = inst[kk];
     const int lbk = (int)((long long)blockIdx.x - I.wg0);
+    if (lbk == 0) clear_inst_B(B, I, threadIdx.x, 256);
     const int xcd = lbk & 7;
     const int local = lbk >> 3;
     const int t = (local / kSweepParts) * 8 + xcd;
@@ -487,7 +576,7 @@ __global__ __launch_bounds__(256) void k_sweep_cube(T* __restrict__ Dd, const T*
         for (int u = 0; u < 2; ++u) {
             if (!ok[u]) continue;
             const int jj = j[u], nn = n[u], qq = q[u];
-            const T mean = six_way_mean<T>(A0[u], B0[u], C0[u], share(0, jj, nn), share(1, jj, qq), share(2, nn, jj),
+            const T mean = six_way_mean<PM>(A0[u], B0[u], C0[u], share(0, jj, nn), share(1, jj, qq), share(2, nn, jj),
                                            share(3, nn, qq), share(4, qq, jj), share(5, qq, nn));
             Dk[aA[u]] = mean;
             Dk[aB[u]] = mean;
@@ -553,19 +642,21 @@ __host__ __device__ inline size_t sweep_triple_lds(int N)
 
 // Workgroup b takes triple b - pre[s] of instance ids[s] (of instance s when
 // ids is null), s the last of the K prefix entries with pre[s] <= b.
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_sweep_triple(T* __restrict__ Dd, const T* __restrict__ CC,
-                                                     T* __restrict__ B, const int* __restrict__ tri,
+template <int PM, int NT>
+__global__ __launch_bounds__(NT) void k_sweep_triple(StoreT<PM>* __restrict__ Dd, const StoreT<PM>* __restrict__ CC,
+                                                     StoreT<PM>* __restrict__ B, const int* __restrict__ tri,
                                                      const Inst* __restrict__ inst, const long long* __restrict__ pre,
-                                                     const int* __restrict__ ids, int K, long long totalB)
+                                                     const int* __restrict__ ids, int K, const int* __restrict__ act)
 {
+    using T = StoreT<PM>;
     extern __shared__ __align__(16) unsigned char smem[];
-    const long long gx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gx < totalB) B[gx] = (T)0;
     const int s = find_seg(pre, K, (long long)blockIdx.x);
-    const Inst I = inst[ids ? ids[s] : s];
+    const int id = ids ? ids[s] : s;
+    if (!act[id]) return;   // whole workgroup
+    const Inst I = inst[id];
     const int t = (int)((long long)blockIdx.x - pre[s]);
     if (t >= I.ntri) return;   // whole workgroup
+    if (t == 0) clear_inst_B(B, I, threadIdx.x, NT);
     const int N = I.N, n1 = N - 1, n2 = N - 2;
     const int NN = N * N;
     const int run = N * n1 * n2, rowlen = n1 * n2;   // one location j: N-1 rows of N-2
@@ -662,7 +753,7 @@ __global__ __launch_bounds__(NT) void k_sweep_triple(T* __restrict__ Dd, const T
             T& a = As[jl * rowlen + r];
             T& b = Bs[jl * rowlen + jq * n2 + (n - (n > j) - (n > q))];
             T& c = Cs[(n * n1 + q - (q > n)) * n2 + (j - (j > n) - (j > q))];
-            const T mean = six_way_mean<T>(a, b, c, X[0 * NN + j * N + n], X[1 * NN + j * N + q],
+            const T mean = six_way_mean<PM>(a, b, c, X[0 * NN + j * N + n], X[1 * NN + j * N + q],
                                            X[2 * NN + n * N + j], X[3 * NN + n * N + q],
                                            X[4 * NN + q * N + j], X[5 * NN + q * N + n]);
             a = mean;
@@ -706,6 +797,9 @@ __global__ __launch_bounds__(NT) void k_sweep_triple(T* __restrict__ Dd, const T
 template <typename T>
 struct TripleRef {
     int N, n1, n2, NN, run, rowlen, ntiles, i, k, p;
+    int live;        // the instance is active
+    int first;       // the instance's first triple (its workgroup clears B)
+    long long offB;  // the instance's B
     T* gA;
     T* gB;
     T* gC;
@@ -715,12 +809,17 @@ struct TripleRef {
 template <typename T>
 __device__ __forceinline__ TripleRef<T> triple_ref(T* Dd, const T* CC, const int* __restrict__ tri,
                                                    const Inst* __restrict__ inst, const long long* __restrict__ pre,
-                                                   const int* __restrict__ ids, int K, long long Tg)
+                                                   const int* __restrict__ ids, int K, long long Tg,
+                                                   const int* __restrict__ act)
 {
     const int s = find_seg(pre, K, Tg);
-    const Inst I = inst[ids ? ids[s] : s];
+    const int id = ids ? ids[s] : s;
+    const Inst I = inst[id];
     const int t = (int)(Tg - pre[s]);
     TripleRef<T> r;
+    r.live = act[id];
+    r.first = t == 0;
+    r.offB = I.offB;
     r.N = I.N;
     r.n1 = r.N - 1;
     r.n2 = r.N - 2;
@@ -741,19 +840,20 @@ __device__ __forceinline__ TripleRef<T> triple_ref(T* Dd, const T* CC, const int
     return r;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict__ Dd, const T* __restrict__ CC,
-                                                                   T* __restrict__ B, const int* __restrict__ tri,
+template <int PM>
+__global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(StoreT<PM>* __restrict__ Dd,
+                                                                   const StoreT<PM>* __restrict__ CC,
+                                                                   StoreT<PM>* __restrict__ B,
+                                                                   const int* __restrict__ tri,
                                                                    const Inst* __restrict__ inst,
                                                                    const long long* __restrict__ pre,
                                                                    const int* __restrict__ ids, int K,
-                                                                   long long totalB, long long totalTri, int Nmax)
+                                                                   long long totalTri, int Nmax,
+                                                                   const int* __restrict__ act)
 {
+    using T = StoreT<PM>;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
-    for (long long x = (long long)blockIdx.x * kTripleThreads + tid; x < totalB;
-         x += (long long)gridDim.x * kTripleThreads)
-        B[x] = (T)0;
     long long Tg = blockIdx.x;
     if (Tg >= totalTri) return;   // whole workgroup
     T* __restrict__ Cs = reinterpret_cast<T*>(smem);
@@ -803,7 +903,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict
         }
     };
 
-    TripleRef<T> cur = triple_ref<T>(Dd, CC, tri, inst, pre, ids, K, Tg);
+    TripleRef<T> cur = triple_ref<T>(Dd, CC, tri, inst, pre, ids, K, Tg, act);
     T pa0[2], pb0[2], pa1[2], pb1[2];
     loadC(cur.gC, cur.run, 0);
     loadX(cur.CCk, cur.N, cur.i, cur.k, cur.p);
@@ -815,6 +915,9 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict
         T* const gA = cur.gA;
         T* const gB = cur.gB;
         T* const gC = cur.gC;
+        const bool live = cur.live != 0;   // an ended instance's entries are written back unchanged
+        if (live && cur.first)
+            for (int e = tid; e < cur.NN; e += kTripleThreads) B[cur.offB + e] = (T)0;
         putC(run, 0);
         putX(N);
 #pragma unroll
@@ -826,7 +929,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict
         const bool more = Tn < totalTri;
         // The next triple (when there is none, every "next" load below reads
         // one entry of this triple's runs: the code stays straight-line).
-        const TripleRef<T> nxt = triple_ref<T>(Dd, CC, tri, inst, pre, ids, K, more ? Tn : Tg);
+        const TripleRef<T> nxt = triple_ref<T>(Dd, CC, tri, inst, pre, ids, K, more ? Tn : Tg, act);
         T* const hA = nxt.gA;
         T* const hB = nxt.gB;
         const int hN = more ? nxt.N : 1, hrow = more ? nxt.rowlen : 1;
@@ -851,7 +954,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict
             const bool on = t2 < ntiles;
             fetch(ra, rb, on ? gA : hA, on ? gB : hB, on ? N : hN, on ? rowlen : hrow,
                   on ? t2 * kTripleJT : min((t2 - ntiles) * kTripleJT, hlast));
-            for (int g = tid; g < len; g += kTripleThreads) {
+            for (int g = tid; live && g < len; g += kTripleThreads) {
                 const int jl = g / rowlen, r = g - jl * rowlen;
                 const int j = j0 + jl;
                 const int nc = r / n2, qc = r - nc * n2;   // n' (skipping j), q'' (skipping j and n)
@@ -863,7 +966,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict
                 T& a = As[jl * rowlen + r];
                 T& b = Bs[jl * rowlen + jq * n2 + (n - (n > j) - (n > q))];
                 T& c = Cs[(n * n1 + q - (q > n)) * n2 + (j - (j > n) - (j > q))];
-                const T mean = six_way_mean<T>(a, b, c, X[0 * NN + j * N + n], X[1 * NN + j * N + q],
+                const T mean = six_way_mean<PM>(a, b, c, X[0 * NN + j * N + n], X[1 * NN + j * N + q],
                                                X[2 * NN + n * N + j], X[3 * NN + n * N + q],
                                                X[4 * NN + q * N + j], X[5 * NN + q * N + n]);
                 a = mean;
@@ -913,13 +1016,17 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(T* __restrict
 
 // Step 5: the complementary pair c_ijkn, c_knij (equation (10)) both become
 // their mean.  One thread per C entry; the thread with i < k does the pair.
-template <typename T>
-__global__ __launch_bounds__(256) void k_transfer_C(T* __restrict__ C, const Inst* __restrict__ inst,
-                                                    const long long* __restrict__ preC, int K, long long totalC)
+template <int PM>
+__global__ __launch_bounds__(256) void k_transfer_C(StoreT<PM>* __restrict__ C, const Inst* __restrict__ inst,
+                                                    const long long* __restrict__ preC, int K, long long totalC,
+                                                    const int* __restrict__ act)
 {
+    using T = StoreT<PM>;
     const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= totalC) return;
-    const Inst I = inst[find_seg(preC, K, x)];
+    const int kk = find_seg(preC, K, x);
+    if (!act[kk]) return;
+    const Inst I = inst[kk];
     const int N = I.N, n1 = N - 1;
     const long long lx = x - I.offC;
     const int ij = (int)(lx / (n1 * n1));
@@ -929,10 +1036,10 @@ __global__ __launch_bounds__(256) void k_transfer_C(T* __restrict__ C, const Ins
     if (i >= k) return;
     const long long y = I.offC + beta_of(N, k, n, i, j);
     T mean;
-    if constexpr (sizeof(T) == 8)
-        mean = (C[x] + C[y]) / (T)2;
-    else
+    if constexpr (PM == kPrecF32Down)
         mean = to_float_down(div_down(add_down((double)C[x], (double)C[y]), 2.0));
+    else
+        mean = (T)(((double)C[x] + (double)C[y]) / 2.0);
     C[x] = mean;
     C[y] = mean;
 }
@@ -1000,6 +1107,7 @@ __global__ __launch_bounds__(256) void k_cert_C(const double* __restrict__ ct, c
 }
 
 // One wave per instance: out[k] = LB_k + N min(0, min bt over the instance).
+template <typename Unused = void>
 __global__ __launch_bounds__(64) void k_cert_final(const double* __restrict__ bt, const double* __restrict__ lb,
                                                    double* __restrict__ out, const Inst* __restrict__ inst)
 {

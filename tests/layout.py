@@ -6,9 +6,12 @@ block C_ij holds rows k != i and columns n != j in ascending order; block
 D_ijkn (the beta(ijkn)-th block) holds rows p not in {i,k} and columns q not
 in {j,n} in ascending order.
 """
+import functools
+
 import numpy as np
 
 
+@functools.lru_cache(maxsize=8)
 def c_index_arrays(N):
     """(I, J, K, Nn) dense indices for every compact C position, in order."""
     I, J, K, Nn = [], [], [], []
@@ -73,3 +76,36 @@ def close_family(x, y, tol):
     scale = np.maximum(np.abs(y), np.abs(y).mean() if y.size else 0.0)
     bad = np.abs(x - y) > tol * scale
     return (not bad.any()), (np.abs(x - y) / np.maximum(scale, 1e-300)).max() if y.size else 0.0
+
+
+def represented(N, lb, B, C, D, perms):
+    """LB + sum_i b_{i p(i)} + sum_{i!=k} c_{i p(i) k p(k)} + sum over ordered
+    distinct triples of d_{i p(i) k p(k) r p(r)}, for every row p of `perms`
+    (compact state arrays, FP64).  D may be None (level-1 state)."""
+    P = np.asarray(perms, dtype=np.int64)
+    if P.ndim == 1:
+        P = P[None, :]
+    n1, n2 = N - 1, N - 2
+    B = np.asarray(B).reshape(N, N)
+    tot = np.full(P.shape[0], float(lb))
+    for i in range(N):
+        tot += B[i, P[:, i]]
+    for i in range(N):
+        for k in range(N):
+            if k == i:
+                continue
+            pi, pk = P[:, i], P[:, k]
+            beta = (i * N + pi) * n1 * n1 + (k - (k > i)) * n1 + (pk - (pk > pi))
+            tot += C[beta]
+            if D is None:
+                continue
+            lo, hi = min(i, k), max(i, k)
+            plo, phi = np.minimum(pi, pk), np.maximum(pi, pk)
+            for r in range(N):
+                if r == i or r == k:
+                    continue
+                pr = P[:, r]
+                row = r - (r > lo) - (r > hi)
+                col = pr - (pr > plo) - (pr > phi)
+                tot += D[beta * n2 * n2 + row * n2 + col]
+    return tot

@@ -1,0 +1,266 @@
+"""The steps either side of a node's dual ascent, and the branch and bound of
+Section 6, on the GPU: the stop rule of Algorithm 1, children that inherit
+their parent's reduced costs, the level-1 strong-branching evaluation, the
+incumbent from the B-level assignment, and the depth-first search with its
+checkpoint and resume.
+
+References: brute-force optima (oracle.brute, enumeration), node
+subproblems built here in numpy, and the children's inherited state built in
+numpy from the parent's state read back from the GPU.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import qapgen
+from oracle import brute
+from paper_1510_02065_amd import QapError, Rlt2, bnb_solve, objective, subproblem
+from tests import layout
+
+pytestmark = pytest.mark.gpu
+
+
+# ---- stop rule ------------------------------------------------------------------
+
+def test_stop_rule_upper_bound():
+    F, D = qapgen.small(8, 1)
+    free = Rlt2(F, D)
+    free.ascend(12)
+    lb, _ = free.trace()
+    # UB between LB_4 and LB_5: the run stops after iteration 5 (LB >= UB).
+    UB = 0.5 * (lb[4] + lb[5])
+    assert lb[4] < UB <= lb[5]
+    g = Rlt2(F, D, UB=UB)
+    g.ascend(12)
+    act, its = g.status()
+    assert act[0] == 0 and its[0] == 5
+    glb, _ = g.trace()
+    np.testing.assert_array_equal(glb, lb[:6])
+    state = g.read_state()
+    g.ascend(3)   # a stopped instance keeps its state
+    for x, y in zip(state, g.read_state()):
+        np.testing.assert_array_equal(x, y)
+    assert g.bound()[1] == 5
+    free.close()
+    g.close()
+
+
+def test_stop_rule_progress():
+    F, D = qapgen.uniform(10, 2)
+    free = Rlt2(F, D)
+    free.ascend(30)
+    lb, lbp = free.trace()
+    UB = 2.0 * lb[-1]
+    K = float(np.median(lbp[1:]) / UB)
+    # The loop runs while LB'/UB >= K: the first iteration with LB' < K*UB is
+    # the last one run.
+    t = next(t for t in range(1, 31) if lbp[t] < K * UB)
+    g = Rlt2(F, D, K=K, UB=UB)
+    g.ascend(30)
+    act, its = g.status()
+    assert act[0] == 0 and its[0] == t
+    np.testing.assert_array_equal(g.trace()[0], lb[: t + 1])
+    free.close()
+    g.close()
+
+
+def test_stop_rule_batch_instances_independent():
+    F, D, fixes = qapgen.nodes(count=5, parent_N=11, seed=4, m_lo=1, m_hi=3)
+    nodes = [subproblem(F, D, fac, loc) for fac, loc in fixes]
+    args = ([n[0] for n in nodes], [n[1] for n in nodes], [n[2] for n in nodes], [n[3] for n in nodes])
+    ref = Rlt2.batch(*args)
+    ref.ascend(10)
+    lbs = [ref.trace_k(k)[0] for k in range(5)]
+    # An upper bound that instance 0 reaches at iteration 3 and that stays
+    # above the others' last bound... set per the traces: stop rule is global.
+    UB = 0.5 * (lbs[0][2] + lbs[0][3])
+    stops = [next((t for t in range(11) if lbs[k][t] >= UB), None) for k in range(5)]
+    g = Rlt2.batch(*args, UB=UB)
+    g.ascend(10)
+    act, its = g.status()
+    for k in range(5):
+        if stops[k] is None:
+            assert act[k] == 1 and its[k] == 10
+            for x, y in zip(ref.read_state_k(k), g.read_state_k(k)):
+                np.testing.assert_array_equal(x, y)
+        else:
+            assert act[k] == 0 and its[k] == stops[k]
+            np.testing.assert_array_equal(g.trace_k(k)[0], lbs[k][: stops[k] + 1])
+    ref.close()
+    g.close()
+
+
+# ---- children with inherited reduced costs ------------------------------------------
+
+def _child_state_numpy(N, lb, B, C, D, a, b):
+    """LB', B', C', D' of the child fixing a -> b, from the parent's compact
+    state, by the definition of the split (numpy, FP64)."""
+    n1, n2 = N - 1, N - 2
+    M = N - 1
+    I, J, K, Nn = layout.c_index_arrays(N)
+    cpos = {(int(I[x]), int(J[x]), int(K[x]), int(Nn[x])): x for x in range(len(I))}
+    Bm = B.reshape(N, N)
+    fr = [i for i in range(N) if i != a]
+    lr = [j for j in range(N) if j != b]
+
+    def d(i, j, k, n, p, q):
+        beta = cpos[(i, j, k, n)]
+        rows = [r for r in range(N) if r != i and r != k]
+        cols = [c for c in range(N) if c != j and c != n]
+        return D[beta * n2 * n2 + rows.index(p) * n2 + cols.index(q)]
+
+    Bc = np.empty((M, M))
+    for x, i in enumerate(fr):
+        for y, j in enumerate(lr):
+            Bc[x, y] = Bm[i, j] + C[cpos[(i, j, a, b)]] + C[cpos[(a, b, i, j)]]
+    Cc = np.empty(M * M * (M - 1) ** 2)
+    Ic, Jc, Kc, Ncl = layout.c_index_arrays(M)
+    for x in range(len(Ic)):
+        i, j, k, n = fr[Ic[x]], lr[Jc[x]], fr[Kc[x]], lr[Ncl[x]]
+        v = C[cpos[(i, j, k, n)]]
+        if D is not None:
+            v = v + d(a, b, i, j, k, n) + d(i, j, a, b, k, n) + d(i, j, k, n, a, b)
+        Cc[x] = v
+    return lb + Bm[a, b], Bc.ravel(), Cc
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32n"])
+@pytest.mark.parametrize("level", [2, 1])
+def test_children_inherit_parent_state(precision, level):
+    F, D = qapgen.small(8, 6)
+    N = 8
+    g = Rlt2(F, D, precision=precision)
+    g.ascend(3)
+    lb, B, C, Dst = g.read_state()
+    fac = [0, 0, 3, 7, 5]
+    loc = [0, 4, 2, 7, 1]
+    ch = g.children(0, fac, loc, level=level)
+    tol = 1e-12 if precision == "fp64" else 3e-7
+    for c, (a, b) in enumerate(zip(fac, loc)):
+        lbc, Bc, Cc, Dc = ch.read_state_k(c, want_D=(level == 2))
+        rlb, rB, rC = _child_state_numpy(N, lb, B, C, Dst, a, b)
+        assert lbc == pytest.approx(rlb, rel=1e-15)
+        np.testing.assert_allclose(Bc, rB, rtol=tol, atol=tol * np.abs(rB).max())
+        np.testing.assert_allclose(Cc, rC, rtol=tol, atol=tol * np.abs(rC).max())
+        # Objective identity: the child's represented objective on every
+        # completion equals the parent's on the extended permutation.
+        fr = [i for i in range(N) if i != a]
+        lr = [j for j in range(N) if j != b]
+        perms = brute.all_perms(N - 1)[::37]
+        full = np.empty((len(perms), N), dtype=np.int64)
+        full[:, a] = b
+        full[:, fr] = np.array(lr)[perms]
+        rep_parent = layout.represented(N, lb, B, C, Dst, full)
+        rep_child = layout.represented(N - 1, lbc, Bc, Cc, Dc if level == 2 else None, perms)
+        np.testing.assert_allclose(rep_child, rep_parent, rtol=1e-6 if precision != "fp64" else 1e-12)
+    # The children's own dual ascent keeps a valid bound for each node.
+    ch.ascend(5)
+    lbs = ch.bounds()
+    for c, (a, b) in enumerate(zip(fac, loc)):
+        Fs, Ds, Bs, const = subproblem(F, D, [a], [b])
+        opt, _ = brute.qap_brute(Fs, Ds, Bs, const)
+        assert lbs[c] <= opt * (1 + 1e-6)
+        assert lbs[c] >= ch.trace_k(c)[0][0] - 1e-9 * abs(lbs[c])   # never below the inherited bound
+    ch.close()
+    g.close()
+
+
+def test_children_errors():
+    F, D = qapgen.small(8, 0)
+    g = Rlt2(F, D)
+    with pytest.raises(QapError):
+        g.children(0, [8], [0])
+    with pytest.raises(QapError):
+        g.children(1, [0], [0])
+    h = Rlt2(F, D, level=1)
+    with pytest.raises(QapError):
+        h.children(0, [0], [0], level=2)   # a level-1 parent has no D
+    g.close()
+    h.close()
+
+
+def test_level1_handle_matches_rlt1_numpy():
+    # The level-1 dual ascent's iteration 0 is the Gilmore-Lawler bound, and
+    # its bound stays below the optimum and never falls.
+    F, D = qapgen.small(8, 2)
+    h = Rlt2(F, D, level=1)
+    glb = brute.gilmore_lawler(F, D)
+    assert h.bound()[0] == pytest.approx(glb, rel=1e-12)
+    h.ascend(20)
+    lb, lbp = h.trace()
+    opt, _ = brute.qap_brute(F, D)
+    assert (np.diff(lb) >= -1e-9).all() and lb[-1] <= opt * (1 + 1e-12)
+    h.close()
+
+
+def test_strong_branch_choice_and_bounds():
+    F, D = qapgen.small(8, 8)
+    N = 8
+    g = Rlt2(F, D)
+    g.ascend(2)
+    kind, index, bounds = g.strong_branch(0, iters=3)
+    # Each child's bound is a valid bound of its node.
+    for a in range(N):
+        for b in range(N):
+            Fs, Ds, Bs, const = subproblem(F, D, [a], [b])
+            opt, _ = brute.qap_brute(Fs, Ds, Bs, const)
+            assert bounds[a, b] <= opt * (1 + 1e-9)
+    # The choice follows the rule: the largest smallest child bound, ties to
+    # the larger sum, rows first, lower index first.
+    cands = [(bounds[x].min(), bounds[x].sum(), 0, x) for x in range(N)] + \
+            [(bounds[:, x].min(), bounds[:, x].sum(), 1, x) for x in range(N)]
+    best = max(cands, key=lambda c: (c[0], c[1], -c[2], -c[3]))
+    assert (kind, index) == (best[2], best[3])
+    g.close()
+
+
+def test_assignment_is_a_permutation_with_upper_bound_objective():
+    F, D = qapgen.small(8, 3)
+    g = Rlt2(F, D)
+    g.ascend(4)
+    perm = g.assignment(0)
+    assert sorted(perm) == list(range(8))
+    opt, _ = brute.qap_brute(F, D)
+    assert objective(F, D, perm) >= opt
+    g.close()
+
+
+# ---- branch and bound -------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,strong", [("fp64", 2), ("fp64", -1), ("fp32", 2), ("fp32n", 2)])
+def test_bnb_finds_the_optimum(precision, strong):
+    F, D = qapgen.small(9, 12)
+    print(f"bnb N=9 {precision} strong={strong}", flush=True)
+    opt, _ = brute.qap_brute(F, D)
+    r = bnb_solve(F, D, precision=precision, strong_iters=strong, root_iters=10, iters=4, leaf_size=5)
+    assert r["complete"]
+    assert r["value"] == opt
+    assert objective(F, D, r["perm"]) == opt
+    assert r["root_bound"] <= opt
+
+
+def test_bnb_clustered10():
+    F, D = qapgen.clustered(10, 3)
+    print("bnb clustered N=10", flush=True)
+    opt, _ = brute.qap_brute(F, D)
+    r = bnb_solve(F, D, root_iters=20, iters=5, leaf_size=5)
+    assert r["complete"] and r["value"] == opt
+    print(f"nodes {r['nodes']} pruned {r['pruned']} leaves {r['leaves']} root bound {r['root_bound']} opt {opt}")
+
+
+def test_bnb_checkpoint_and_resume(tmp_path):
+    F, D = qapgen.small(10, 5)
+    print("bnb checkpoint N=10", flush=True)
+    ck = tmp_path / "bnb.ck"
+    full = bnb_solve(F, D, root_iters=5, iters=2, leaf_size=5, strong_iters=-1)
+    assert full["complete"]
+    part = bnb_solve(F, D, root_iters=5, iters=2, leaf_size=5, strong_iters=-1, max_nodes=25,
+                     checkpoint=str(ck), checkpoint_every=10)
+    assert not part["complete"] and ck.exists()
+    res = bnb_solve(F, D, root_iters=5, iters=2, leaf_size=5, strong_iters=-1, checkpoint=str(ck), resume=1)
+    assert res["complete"]
+    assert res["value"] == full["value"]
+    assert objective(F, D, res["perm"]) == full["value"]
+    assert res["nodes"] > part["nodes"]
+    assert not ck.exists()   # removed once the search is complete

@@ -1,0 +1,220 @@
+"""Whole-trajectory parity against the FP64 oracle, at the workloads' full
+sizes and lengths.
+
+* N=16 uniform (50 iterations): every per-LAP value of every iteration, in
+  FP32 round-to-nearest mode, within 1e-5; the certified (rounded-down) mode
+  within its measured drift envelope, and below the oracle's bound.
+* N=25 clustered (100 iterations, the benchmark's workload): the bound of
+  every iteration against the stored oracle trace and the live oracle, and
+  every per-LAP value at iterations 10, 50 and 100, in FP64 (1e-9), FP32
+  round-to-nearest (1e-5) and FP32 certified (bound 1e-5).
+* N=27 and N=35 (FP64 and FP32 round-to-nearest, 2 iterations): the large-N
+  sweep kernel and the 64-lane / multi-column assignment classes, per-LAP
+  values, B and C element by element.
+* N=40 (20 iterations on the GPU; the oracle for 2): per-LAP values, B and C
+  at iterations 1-2, then bound properties and FP32 against FP64 to 20.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import qapgen
+from paper_1510_02065_amd import Rlt2
+from tests import layout
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-9
+TOL32 = 1e-5
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lap_close(g, o, tol, it, with_state=True):
+    sD, sC, sB = g.lap_values()
+    ok, err = layout.close_family(sD, layout.compact_C(o.SD), tol)
+    assert ok, f"D->C values at iteration {it}: rel err {err}"
+    ok, err = layout.close_family(sC, o.SC.ravel(), tol)
+    assert ok, f"C->B values at iteration {it}: rel err {err}"
+    if with_state:
+        _, B, C, _ = g.read_state(want_D=False)
+        ok, err = layout.close_family(B, o.B.ravel(), tol)
+        assert ok, f"B at iteration {it}: {err}"
+        ok, err = layout.close_family(C, layout.compact_C(o.C), tol)
+        assert ok, f"C at iteration {it}: {err}"
+    return err
+
+
+# ---- N=16, 50 iterations, FP32 -------------------------------------------------
+
+def test_uniform16_fp32_nearest_every_lap_every_iteration():
+    F, D = qapgen.uniform(16, 0)
+    print("fp32 nearest uniform N=16, 50 iterations", flush=True)
+    g = Rlt2(F, D, precision="fp32n", trace_level=2)
+    o = oracle.Rlt2Oracle(F, D)
+    o.iteration0()
+    worst = 0.0
+    for it in range(1, 51):
+        cert = g.ascend(1)
+        o.iterate(1)
+        assert abs(cert - o.lb) <= TOL32 * o.lb, (it, cert, o.lb)
+        worst = max(worst, _lap_close(g, o, TOL32, it, with_state=(it % 10 == 0)))
+    print(f"worst per-LAP relative error over 50 iterations: {worst:.3e}", flush=True)
+    g.close()
+
+
+def test_uniform16_fp32_certified_drift_envelope():
+    # Every write rounds toward -inf: per-LAP values drift below the FP64
+    # trajectory by about 2e-7 (relative to the family mean) per iteration.
+    # Asserted: within max(1e-5, 3e-7 t) at every iteration t, and the
+    # certified bound within 1e-5 of the oracle and below it.
+    F, D = qapgen.uniform(16, 0)
+    print("fp32 certified uniform N=16, 50 iterations", flush=True)
+    g = Rlt2(F, D, precision="fp32", trace_level=2)
+    o = oracle.Rlt2Oracle(F, D)
+    o.iteration0()
+    for it in range(1, 51):
+        cert = g.ascend(1)
+        o.iterate(1)
+        assert abs(cert - o.lb) <= TOL32 * o.lb, (it, cert, o.lb)
+        assert cert <= o.lb, (it, cert, o.lb)
+        sD, sC, _ = g.lap_values()
+        env = max(TOL32, 3e-7 * it)
+        ok, err = layout.close_family(sD, layout.compact_C(o.SD), env)
+        assert ok, (it, err)
+        ok, err = layout.close_family(sC, o.SC.ravel(), env)
+        assert ok, (it, err)
+    g.close()
+
+
+# ---- N=25, 100 iterations --------------------------------------------------------
+
+CHECK = (10, 50, 100)
+
+
+@pytest.fixture(scope="module")
+def clustered25_oracle():
+    """The oracle's 100-iteration run of the benchmark workload: its bound
+    trace and the per-LAP values at the checkpoint iterations."""
+    F, D = qapgen.clustered(25, 0)
+    print("oracle clustered N=25, 100 iterations", flush=True)
+    o = oracle.Rlt2Oracle(F, D)
+    o.iteration0()
+    lb = [o.lb]
+    laps = {}
+    for it in range(1, 101):
+        o.iterate(1)
+        lb.append(o.lb)
+        if it in CHECK:
+            laps[it] = (layout.compact_C(o.SD).copy(), o.SC.ravel().copy())
+            print(f"oracle at iteration {it}: LB {o.lb!r}", flush=True)
+    o.close()
+    return F, D, np.array(lb), laps
+
+
+def _trajectory(F, D, ref_lb, laps, precision, tol_lap):
+    g = Rlt2(F, D, precision=precision, trace_level=2, use_graph=True)
+    done = 0
+    worst = {}
+    for it in CHECK:
+        g.ascend(it - done)
+        done = it
+        sD, sC, _ = g.lap_values()
+        if tol_lap is not None:
+            ok, err = layout.close_family(sD, laps[it][0], tol_lap)
+            assert ok, f"{precision}: D->C values at iteration {it}: {err}"
+            ok2, err2 = layout.close_family(sC, laps[it][1], tol_lap)
+            assert ok2, f"{precision}: C->B values at iteration {it}: {err2}"
+            worst[it] = max(err, err2)
+    lb, lbp = g.trace()
+    assert len(lb) == 101
+    assert (np.diff(lb) >= 0).all() and (lbp[1:] >= 0).all()
+    cert = g.certify()
+    g.close()
+    return lb, cert, worst
+
+
+@pytest.mark.timeout(900)
+def test_clustered25_fp64_hundred_iterations(clustered25_oracle):
+    F, D, ref_lb, laps = clustered25_oracle
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "clustered25_seed0_oracle_lb.json")))["lb"]
+    np.testing.assert_array_equal(ref_lb, np.array(gold))   # the stored trace is the oracle's
+    lb, cert, worst = _trajectory(F, D, ref_lb, laps, "fp64", TOL64)
+    rel = np.abs(lb - ref_lb) / ref_lb
+    print(f"fp64: max bound rel err over 100 iterations {rel.max():.2e}; per-LAP {worst}", flush=True)
+    assert rel.max() <= TOL64
+    assert cert == lb[-1]
+
+
+@pytest.mark.timeout(900)
+def test_clustered25_fp32_nearest_hundred_iterations(clustered25_oracle):
+    F, D, ref_lb, laps = clustered25_oracle
+    lb, cert, worst = _trajectory(F, D, ref_lb, laps, "fp32n", TOL32)
+    rel = np.abs(lb - ref_lb) / ref_lb
+    print(f"fp32 nearest: max bound rel err {rel.max():.2e}; per-LAP {worst}", flush=True)
+    assert rel.max() <= TOL32
+    assert abs(cert - ref_lb[-1]) <= TOL32 * ref_lb[-1]
+
+
+@pytest.mark.timeout(900)
+def test_clustered25_fp32_certified_hundred_iterations(clustered25_oracle):
+    F, D, ref_lb, laps = clustered25_oracle
+    lb, cert, _ = _trajectory(F, D, ref_lb, laps, "fp32", None)
+    rel = np.abs(lb - ref_lb) / ref_lb
+    print(f"fp32 certified: max bound rel err {rel.max():.2e}", flush=True)
+    assert rel.max() <= TOL32
+    assert cert <= ref_lb[-1]
+
+
+# ---- large N: the cube sweep and the wide assignment classes ----------------------
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("N", [27, 35])
+def test_large_n_two_iterations_vs_oracle(N):
+    F, D = qapgen.clustered(N, 1)
+    print(f"oracle clustered N={N}", flush=True)
+    o = oracle.Rlt2Oracle(F, D)
+    o.iteration0()
+    hs = {p: Rlt2(F, D, precision=p, trace_level=2) for p in ("fp64", "fp32n")}
+    for it in (1, 2):
+        o.iterate(1)
+        for p, g in hs.items():
+            g.ascend(1)
+            print(f"N={N} {p} iteration {it}", flush=True)
+            lb, _ = g.bound()
+            tol = TOL64 if p == "fp64" else TOL32
+            assert lb == pytest.approx(o.lb, rel=tol)
+            _lap_close(g, o, tol, it)
+    for g in hs.values():
+        g.close()
+    o.close()
+
+
+@pytest.mark.timeout(1200)
+def test_clustered40_against_oracle_and_twenty_iterations():
+    F, D = qapgen.clustered(40, 0)
+    print("clustered N=40: FP64 GPU, oracle for 2 iterations", flush=True)
+    g = Rlt2(F, D, precision="fp64", trace_level=2)
+    o = oracle.Rlt2Oracle(F, D)
+    o.iteration0()
+    for it in (1, 2):
+        o.iterate(1)
+        g.ascend(1)
+        print(f"N=40 iteration {it}", flush=True)
+        assert g.bound()[0] == pytest.approx(o.lb, rel=TOL64)
+        _lap_close(g, o, TOL64, it)
+    o.close()
+    g.ascend(18)
+    lb64, lbp = g.trace()
+    assert len(lb64) == 21 and (np.diff(lb64) >= 0).all() and (lbp[1:] >= 0).all()
+    assert g.certify() == lb64[-1]
+    g.close()
+    for p in ("fp32", "fp32n"):
+        print(f"clustered N=40 {p}, 20 iterations", flush=True)
+        f = Rlt2(F, D, precision=p)
+        cert = f.ascend(20)
+        lb32, _ = f.trace()
+        np.testing.assert_allclose(lb32, lb64, rtol=TOL32)
+        assert abs(cert - lb64[-1]) <= TOL32 * lb64[-1]
+        f.close()
