@@ -19,10 +19,10 @@ struct FamilyClass {
     long long total;
 };
 
-enum : int { kFamD = 0, kFamC = 1 };
+enum LapFamily : int { kFamD = 0, kFamC = 1 };
 
 // How the D family is stored and enumerated (see pair_block).
-enum : int {
+enum DStorage : int {
     kAllBlocks = 0,    // every block stored (block-major); problem b is block b, parent c_b
     kHalfStore = 1,    // one block per complementary pair stored (pair-major);
                        // problem h is stored block h, parents c_beta and c_twin

@@ -26,7 +26,7 @@ template <> __device__ __forceinline__ float inf_of<float>() { return __builtin_
 // permlane32_swap (gfx950) called with the same register twice return, in
 // their two results, the lane's own value and the value 16 (32) lanes away in
 // some order, which is all a commutative reduction needs.
-enum : int { kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140 };
+enum DppCtrl : int { kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140 };
 
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int x) { return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true); }

@@ -107,7 +107,7 @@ __device__ __forceinline__ float add_down_to_float(double a, double b) {
 // validity).  kPrecF32Near: FP32 state, every value computed in FP64 and
 // rounded to nearest once (no systematic drift; validity rests on the FP64
 // certification over the stored state).
-enum : int { kPrecF64 = 0, kPrecF32Down = 1, kPrecF32Near = 2 };
+enum PrecMode : int { kPrecF64 = 0, kPrecF32Down = 1, kPrecF32Near = 2 };
 template <int PM>
 using StoreT = typename std::conditional<PM == kPrecF64, double, float>::type;
 

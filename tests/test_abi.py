@@ -42,3 +42,51 @@ def test_library_loads_and_binding_covers_header(libpath):
     for n in _declared():
         getattr(L, n)
         assert n in _binding.SIGNATURES, n
+
+
+def _tool(name):
+    p = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "llvm", "bin", name)
+    return p if os.path.exists(p) else None
+
+
+def test_every_registered_kernel_has_device_code(libpath, tmp_path):
+    """Every kernel whose host stub an object registers is defined, under the
+    same name, in that object's gfx950 code.  A kernel whose template
+    arguments involve a type with internal linkage (an unnamed enum) gets a
+    translation-unit-local device name, and the runtime then fails to find
+    it at its first launch."""
+    from paper_1510_02065_amd import build
+    bundler, readelf = _tool("clang-offload-bundler"), _tool("llvm-readelf")
+    if not bundler or not readelf:
+        pytest.skip("ROCm LLVM tools not found")
+    checked = 0
+    for src in build.SOURCES:
+        if not src.endswith(".hip"):
+            continue
+        obj = os.path.join(build.OBJDIR, os.path.basename(src) + ".o")
+        fat = str(tmp_path / (os.path.basename(src) + ".fatbin"))
+        co = str(tmp_path / (os.path.basename(src) + ".co"))
+        subprocess.run(["objcopy", "--dump-section", f".hip_fatbin={fat}", obj], capture_output=True)
+        if not os.path.exists(fat):
+            continue   # no device code in this object
+        subprocess.run([bundler, "--type=o", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", f"--input={fat}",
+                        f"--output={co}", "--unbundle"], check=True)
+        syms = subprocess.run([readelf, "-s", "--wide", co], capture_output=True, text=True, check=True).stdout
+        dev = set(l.split()[7] for l in syms.splitlines() if len(l.split()) >= 8 and l.split()[3] == "FUNC")
+        strs = subprocess.run(["strings", obj], capture_output=True, text=True, check=True).stdout.split()
+        stubs = set(s for s in strs if "__device_stub__" in s and "." not in s)
+        host = set(s.replace("__device_stub__", "", 1) for s in stubs)
+        # the stub's name differs from the kernel's by the inserted prefix,
+        # whose length is part of the mangled identifier: rebuild it
+        names = set()
+        for s in stubs:
+            m = re.match(r"_ZN3qap(\d+)__device_stub__(\w+)", s)
+            if not m:
+                continue
+            k = int(m.group(1)) - len("__device_stub__")
+            names.add(f"_ZN3qap{k}" + s[m.end(1) + len("__device_stub__"):])
+        assert names, f"no kernel stubs found in {obj}"
+        missing = sorted(n for n in names if n not in dev)
+        assert not missing, (os.path.basename(src), missing[:3])
+        checked += len(names)
+    assert checked > 0
