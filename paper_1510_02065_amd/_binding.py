@@ -184,19 +184,19 @@ class Rlt2:
               use_graph=True, device=-1, stream=None, autotune=True, tune_cache=None,
               complementary=True, K=0.0, UB=0.0, level=2):
         """Many instances (e.g. branch-and-bound nodes) in one handle."""
-        K = len(Fs)
+        count = len(Fs)
         Fs = [_f64(F) for F in Fs]
         Ds = [_f64(D) for D in Ds]
         Ns = np.array([F.shape[0] for F in Fs], dtype=np.int32)
-        B0s = [None if B is None else _f64(B) for B in (B0s or [None] * K)]
-        consts = np.array(constants if constants is not None else [0.0] * K, dtype=np.float64)
-        fp = (ctypes.c_void_p * K)(*[F.ctypes.data for F in Fs])
-        dp = (ctypes.c_void_p * K)(*[D.ctypes.data for D in Ds])
-        bp = (ctypes.c_void_p * K)(*[None if B is None else B.ctypes.data for B in B0s])
+        B0s = [None if B is None else _f64(B) for B in (B0s or [None] * count)]
+        consts = np.array(constants if constants is not None else [0.0] * count, dtype=np.float64)
+        fp = (ctypes.c_void_p * count)(*[F.ctypes.data for F in Fs])
+        dp = (ctypes.c_void_p * count)(*[D.ctypes.data for D in Ds])
+        bp = (ctypes.c_void_p * count)(*[None if B is None else B.ctypes.data for B in B0s])
         opts = _opts(precision, trace_level, use_graph, device, stream, autotune, tune_cache, complementary,
                      K, UB, level)
         h = _vp()
-        _check(lib().qap_rlt2_batch_create(K, Ns.ctypes.data, ctypes.cast(fp, _vp), ctypes.cast(dp, _vp),
+        _check(lib().qap_rlt2_batch_create(count, Ns.ctypes.data, ctypes.cast(fp, _vp), ctypes.cast(dp, _vp),
                                            ctypes.cast(bp, _vp), consts.ctypes.data, ctypes.byref(opts),
                                            ctypes.byref(h)), "qap_rlt2_batch_create")
         self = cls.__new__(cls)

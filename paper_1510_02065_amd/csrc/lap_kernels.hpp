@@ -187,7 +187,7 @@ __global__ __launch_bounds__(64) void k_lap_B_s(StoreT<PM>* __restrict__ B, cons
             counter[k] = t + 1;
         }
         const double Kp = stop[0], UB = stop[1];
-        if (UB > 0.0 && (L >= UB || S < Kp * UB)) act[k] = 0;
+        if (UB > 0.0 && (L >= UB || (Kp > 0.0 && S < Kp * UB))) act[k] = 0;
     }
 }
 

@@ -79,6 +79,8 @@ def test_stop_rule_batch_instances_independent():
     g = Rlt2.batch(*args, UB=UB)
     g.ascend(10)
     act, its = g.status()
+    print(f"UB {UB!r}; LB_0 {[l[0] for l in lbs]}; expected stops {stops}; active {act}; iterations {its}",
+          flush=True)
     for k in range(5):
         if stops[k] is None:
             assert act[k] == 1 and its[k] == 10
@@ -125,6 +127,25 @@ def _child_state_numpy(N, lb, B, C, D, a, b):
     return lb + Bm[a, b], Bc.ravel(), Cc
 
 
+def _free_d_sum(N, Dst, a, perms):
+    """Sum of the parent's d_{i p(i) k p(k) r p(r)} over ordered distinct
+    triples of facilities other than a, for every row of perms."""
+    I, J, K, Nn = layout.c_index_arrays(N)
+    n2 = N - 2
+    Dm = np.asarray(Dst, dtype=np.float64).reshape(len(I), n2, n2).copy()
+    for b in range(len(I)):
+        i, k = int(I[b]), int(K[b])
+        if a in (i, k):
+            Dm[b] = 0.0
+            continue
+        rows = layout.d_block_rows(N, i, k)
+        if a in rows:
+            Dm[b, rows.index(a), :] = 0.0
+    zB = np.zeros(N * N)
+    zC = np.zeros(len(I))
+    return layout.represented(N, 0.0, zB, zC, Dm.ravel(), perms)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32n"])
 @pytest.mark.parametrize("level", [2, 1])
 def test_children_inherit_parent_state(precision, level):
@@ -153,6 +174,11 @@ def test_children_inherit_parent_state(precision, level):
         full[:, fr] = np.array(lr)[perms]
         rep_parent = layout.represented(N, lb, B, C, Dst, full)
         rep_child = layout.represented(N - 1, lbc, Bc, Cc, Dc if level == 2 else None, perms)
+        if level == 1:
+            # A level-1 child drops the parent's D terms among the free
+            # facilities (all >= 0): it represents exactly that much less.
+            rep_parent = rep_parent - _free_d_sum(N, Dst, a, full)
+            assert (rep_child <= layout.represented(N, lb, B, C, Dst, full) * (1 + 1e-12)).all()
         np.testing.assert_allclose(rep_child, rep_parent, rtol=1e-6 if precision != "fp64" else 1e-12)
     # The children's own dual ascent keeps a valid bound for each node.
     ch.ascend(5)
@@ -253,12 +279,15 @@ def test_bnb_checkpoint_and_resume(tmp_path):
     F, D = qapgen.small(10, 5)
     print("bnb checkpoint N=10", flush=True)
     ck = tmp_path / "bnb.ck"
-    full = bnb_solve(F, D, root_iters=5, iters=2, leaf_size=5, strong_iters=-1)
+    full = bnb_solve(F, D, root_iters=3, iters=1, leaf_size=3, strong_iters=-1)
     assert full["complete"]
-    part = bnb_solve(F, D, root_iters=5, iters=2, leaf_size=5, strong_iters=-1, max_nodes=25,
-                     checkpoint=str(ck), checkpoint_every=10)
+    # Stop half way through the tree (at least two checkpoints taken).
+    assert full["nodes"] >= 6, full
+    half = full["nodes"] // 2
+    part = bnb_solve(F, D, root_iters=3, iters=1, leaf_size=3, strong_iters=-1, max_nodes=half,
+                     checkpoint=str(ck), checkpoint_every=max(1, half // 3))
     assert not part["complete"] and ck.exists()
-    res = bnb_solve(F, D, root_iters=5, iters=2, leaf_size=5, strong_iters=-1, checkpoint=str(ck), resume=1)
+    res = bnb_solve(F, D, root_iters=3, iters=1, leaf_size=3, strong_iters=-1, checkpoint=str(ck), resume=1)
     assert res["complete"]
     assert res["value"] == full["value"]
     assert objective(F, D, res["perm"]) == full["value"]

@@ -66,7 +66,9 @@ def test_fp32_small_certificate_and_accuracy(seed, precision):
     for it in range(1, 6):
         cert = g.ascend(1)
         o.iterate(1)
-        assert cert <= opt
+        # Only the directed-rounding mode is a proof; the nearest mode's
+        # bound may exceed a tight optimum by its rounding drift (<= 1e-5).
+        assert cert <= (opt if precision == "fp32" else opt * (1 + TOL32)), (it, cert, opt)
         assert abs(cert - o.lb) <= TOL32 * o.lb, (it, cert, o.lb)
         sD, sC, sB = g.lap_values()
         ok, err = layout.close_family(sD, layout.compact_C(o.SD), TOL32)
