@@ -6,8 +6,15 @@ concentrations C->B, B->LB') on the clustered N=25 instance (seed 0), with the
 whole state resident in HBM.  The timed region launches the iterations step by
 step with HIP events around every step on the stream the library launches on,
 so the per-kernel durations behind the roofline figure come from the timed
-iterations themselves; the same iterations launched as one HIP graph each are
-timed after it as `graph_iters_per_s`.  Prints one JSON line.
+iterations themselves; the next iterations, launched as one HIP graph each
+(the library's ascend), are timed after it as `graph_iters_per_s`.
+
+Every other leg is timed the same two ways over the same iteration counts, so
+rates compare like for like: certified FP32 and round-to-nearest FP32 on the
+same instance, FP64 with every D block stored and solved, N=40 in FP64 and
+certified FP32 (20 iterations), and the batched branch-and-bound nodes.  The
+oracle is timed on the host single-threaded and on every core of the affinity
+set.  Prints one JSON line (progress goes to stderr).
 
 `--calibrate-copy` instead runs the plain 1 GiB device copy whose FETCH_SIZE and
 WRITE_SIZE counter readings scale the per-dispatch HBM traffic figures.
@@ -63,27 +70,49 @@ def parse():
     ap.add_argument("--all-blocks", action="store_true",
                     help="concentrate every D block instead of each complementary pair once")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the certified FP32 leg")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 legs (certified and nearest)")
+    ap.add_argument("--no-all-blocks", action="store_true", help="skip the every-block FP64 leg")
+    ap.add_argument("--no-large", action="store_true", help="skip the N=40 legs")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched branch-and-bound leg")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="oracle iterations in the CPU baseline (0: pick ~15 s of work)")
     return ap.parse_args()
 
 
-def cpu_baseline(F, D, iters):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(F, D, iters, budget_s=12.0):
+    """The oracle on the host: single-threaded, then on every core of the
+    process's affinity set; each timed over a bounded number of iterations
+    (about `budget_s` seconds) after iteration 0 and one untimed iteration."""
     import oracle
-    o = oracle.Rlt2Oracle(F, D)
-    o.iteration0()
-    o.iterate(1)                       # first touch of the dense state, not timed
-    if iters <= 0:
+    cores = len(os.sched_getaffinity(0))
+    out = {}
+    for label, threads in (("single_thread", 1), ("all_cores", cores)):
+        oracle.set_threads(threads)
+        o = oracle.Rlt2Oracle(F, D)
+        o.iteration0()
         t = time.perf_counter()
-        o.iterate(1)
+        o.iterate(1)                   # first touch of the dense state, not counted
         per = time.perf_counter() - t
-        iters = max(1, min(30, int(15.0 / max(per, 1e-3))))
-    t = time.perf_counter()
-    o.iterate(iters)
-    dt = time.perf_counter() - t
-    return iters / dt, iters, oracle.threads()
+        n = iters if iters > 0 else max(1, min(30, int(budget_s / max(per, 1e-3))))
+        t = time.perf_counter()
+        o.iterate(n)
+        dt = time.perf_counter() - t
+        out[label] = {"iters_per_s": n / dt, "iterations": n, "threads": oracle.threads()}
+        o.close()
+    oracle.set_threads(cores)
+    out["model"] = _cpu_model()
+    out["affinity_cores"] = cores
+    return out
 
 
 def batched_leg(stream, iters=20):
@@ -150,37 +179,23 @@ def calibrate_copy():
           f"{2.0 * x.numel() * 8 / (ms * 1e-3) / 1e9:.0f} GB/s of reads plus writes", flush=True)
 
 
-def main():
-    args = parse()
-    if args.calibrate_copy:
-        calibrate_copy()
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
-    import numpy as np
-    import torch
+NAMES = {3: "sweep (steps 1-3)", 4: "concentrate D->C", 5: "transfer C", 6: "concentrate C->B",
+         7: "concentrate B->LB"}
 
-    import qapgen
-    from paper_1510_02065_amd import Rlt2
 
-    N = args.N
-    F, D = qapgen.clustered(N, args.seed)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    stream = torch.cuda.Stream(device=dev)
+def sizes(N, pair):
     n1, n2 = N - 1, N - 2
     nC = N * N * n1 * n1
     nD = nC * n2 * n2
-    pair = not args.all_blocks
-    d_laps = nC // 2 if pair else nC
-    laps_per_iter = d_laps + N * N + 1
-    elem = 8
-    # Algorithmic HBM bytes of each step's kernels: every coefficient the step
-    # must read and every one it must write, once.
-    # With one block stored per complementary pair, D holds nD / 2 entries.
-    nDs = nD // 2 if pair else nD
-    step_bytes = {
+    return nC, nD, (nD // 2 if pair else nD)
+
+
+def step_bytes(N, pair, elem):
+    """Algorithmic HBM bytes of each step's kernels: every coefficient the
+    step must read and every one it must write, once (with one block stored
+    per complementary pair, D holds half the entries)."""
+    nC, _, nDs = sizes(N, pair)
+    return {
         3: 2.0 * nDs * elem + 2.0 * nC * elem,   # stored D read and written, C read and cleared
         4: 2.0 * nDs * elem + 2.0 * nC * elem,   # stored blocks read and written, C read and written
         5: 2.0 * nC * elem,
@@ -188,78 +203,147 @@ def main():
         7: 2.0 * N * N * elem,
     }
 
-    names = {3: "sweep (steps 1-3)", 4: "concentrate D->C", 5: "transfer C", 6: "concentrate C->B",
-             7: "concentrate B->LB"}
-    g = Rlt2(F, D, trace_level=1, use_graph=True, device=0, stream=stream.cuda_stream, complementary=pair)
-    g.ascend(args.warmup)
+
+def laps_per_iteration(N, pair):
+    nC = N * N * (N - 1) * (N - 1)
+    return (nC // 2 if pair else nC) + N * N + 1
+
+
+def timed_leg(F, D, precision, pair, warmup, steps, graph_iters, stream):
+    """One handle on the stream: `warmup` untimed iterations (the first runs
+    the tuner), `steps` iterations launched step by step with HIP events
+    around every step, then `graph_iters` iterations launched as one HIP graph
+    each (the library's ascend).  Both timed regions are bracketed by
+    synchronisation."""
+    import torch
+
+    from paper_1510_02065_amd import Rlt2
+    N = F.shape[0]
+    elem = 8 if precision == "fp64" else 4
+    g = Rlt2(F, D, precision=precision, trace_level=1, use_graph=True, device=0, stream=stream.cuda_stream,
+             complementary=pair)
+    if warmup:
+        g.ascend(warmup)
     torch.cuda.synchronize()
-    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in names]
-          for _ in range(args.steps)]
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in NAMES]
+          for _ in range(steps)]
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record(stream)
-    for t in range(args.steps):
-        for (a, b), s in zip(ev[t], names):
+    for t in range(steps):
+        for (a, b), s in zip(ev[t], NAMES):
             a.record(stream)
             g.step(s)
             b.record(stream)
     stop.record(stream)
     stop.synchronize()
     torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
-    ms_per_step = ms / args.steps
-    it_s = 1000.0 / ms_per_step
-    dur = {s: sum(ev[t][q][0].elapsed_time(ev[t][q][1]) for t in range(args.steps)) / args.steps
-           for q, s in enumerate(names)}
+    ms_step = start.elapsed_time(stop) / steps
+    dur = {s: sum(ev[t][q][0].elapsed_time(ev[t][q][1]) for t in range(steps)) / steps
+           for q, s in enumerate(NAMES)}
+    ms_graph = None
+    if graph_iters > 0:
+        g.bound()   # moves the step-launched iterations' trace entries to the host
+        torch.cuda.synchronize()
+        ga = torch.cuda.Event(enable_timing=True)
+        gb = torch.cuda.Event(enable_timing=True)
+        ga.record(stream)
+        g.ascend(graph_iters)
+        gb.record(stream)
+        gb.synchronize()
+        ms_graph = ga.elapsed_time(gb) / graph_iters
+    lb_trace, _ = g.trace()
+    cert = g.certify()
+    g.close()
+    bytes_ = step_bytes(N, pair, elem)
     dom = max(dur, key=dur.get)
-    iter_frac = 2.0 * nDs * elem * it_s / 1e9 / HBM_PEAK_GBS   # against one read and write of D
+    return {"N": N, "precision": precision, "pair": pair, "elem": elem, "ms_step": ms_step, "ms_graph": ms_graph,
+            "dur": dur, "dom": dom, "bytes": bytes_, "lb_trace": lb_trace, "cert": cert,
+            "iterations": warmup + steps + graph_iters}
+
+
+def roofline(leg, step, digest):
+    N, pair, elem, dur = leg["N"], leg["pair"], leg["elem"], leg["dur"]
+    rec = TRAFFIC.get((step, N, "f64" if elem == 8 else "f32", pair))
+    ach = leg["bytes"][step] / (dur[step] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": NAMES[step], "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS,
+            "traffic": rec[1] + rec[2] if rec is not None and rec[0] == digest else None,
+            "alg_bytes": leg["bytes"][step], "kernel_ms": dur[step]}
+
+
+def leg_summary(leg, digest, ref_leg=None, with_rooflines=True):
+    N, pair = leg["N"], leg["pair"]
+    laps = laps_per_iteration(N, pair)
+    _, _, nDs = sizes(N, pair)
+    it_s = 1000.0 / leg["ms_step"]
+    out = {"iters_per_s": it_s, "laps_per_s": laps * it_s, "ms_per_step": leg["ms_step"],
+           "iteration_hbm_fraction": 2.0 * nDs * leg["elem"] * it_s / 1e9 / HBM_PEAK_GBS,
+           "kernel_ms": {NAMES[s]: round(v, 4) for s, v in leg["dur"].items()}}
+    if leg["ms_graph"] is not None:
+        out["graph_iters_per_s"] = 1000.0 / leg["ms_graph"]
+        out["graph_laps_per_s"] = laps * 1000.0 / leg["ms_graph"]
+    if with_rooflines:
+        out["roofline"] = roofline(leg, leg["dom"], digest)
+        out["roofline_sweep"] = roofline(leg, 3, digest)
+    if ref_leg is not None:
+        t = min(leg["iterations"], ref_leg["iterations"])
+        ref = ref_leg["lb_trace"][t]
+        out["bound"] = leg["lb_trace"][t]
+        out["certified_bound"] = leg["cert"]
+        out["bound_iteration"] = t
+        out["rel_err_vs_fp64_gpu"] = abs(leg["lb_trace"][t] - ref) / abs(ref)
+        errs = [abs(a - b) / abs(b) for a, b in zip(leg["lb_trace"][: t + 1], ref_leg["lb_trace"][: t + 1])]
+        out["rel_err_vs_fp64_gpu_max_over_iterations"] = max(errs)
+        out["certified_below_fp64"] = bool(leg["cert"] <= ref)
+        out["speedup_vs_fp64_step_launched"] = ref_leg["ms_step"] / leg["ms_step"]
+        if leg["ms_graph"] is not None and ref_leg["ms_graph"] is not None:
+            out["speedup_vs_fp64_graph_launched"] = ref_leg["ms_graph"] / leg["ms_graph"]
+    return out
+
+
+def main():
+    args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus must be 1)",
+              file=sys.stderr, flush=True)
+        print(json.dumps({"error": "one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+    import torch
+
+    import qapgen
+
+    N = args.N
+    F, D = qapgen.clustered(N, args.seed)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    pair = not args.all_blocks
     digest = csrc_digest()
-
-    def roofline(step):
-        rec = TRAFFIC.get((step, N, "f64", pair))
-        ach = step_bytes[step] / (dur[step] * 1e-3) / 1e9
-        return {"bound": "hbm", "kernel": names[step], "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS,
-                "traffic": rec[1] + rec[2] if rec is not None and rec[0] == digest else None,
-                "alg_bytes": step_bytes[step], "kernel_ms": dur[step]}
-
-    # Further iterations as one HIP graph launch each (the library's ascend),
-    # up to the iteration at which the bound is compared with the oracle.
+    # Further iterations as one HIP graph launch each, up to the iteration at
+    # which the bound is compared with the oracle.
     extra = max(args.steps, args.bound_iters - args.warmup - args.steps)
     total_iters = args.warmup + args.steps + extra
-    ga = torch.cuda.Event(enable_timing=True)
-    gb = torch.cuda.Event(enable_timing=True)
-    ga.record(stream)
-    g.ascend(extra)
-    gb.record(stream)
-    gb.synchronize()
-    graph_it_s = 1000.0 * extra / ga.elapsed_time(gb)
-    lb_trace, _ = g.trace()
 
-    # Certified FP32 leg on the same instance: the same warm-up and timed
-    # iterations, then on to the same final iteration for the bound.
-    f32 = None
-    if not args.no_fp32:
-        h = Rlt2(F, D, precision="fp32", trace_level=1, use_graph=True, device=0, stream=stream.cuda_stream,
-                 complementary=pair)
-        h.ascend(args.warmup)
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        h.ascend(args.steps)
-        b.record(stream)
-        b.synchronize()
-        ms32 = a.elapsed_time(b) / args.steps
-        cert = h.ascend(extra)
-        ref = lb_trace[total_iters]
-        f32 = {"iters_per_s": 1000.0 / ms32, "laps_per_s": laps_per_iter * 1000.0 / ms32,
-               "ms_per_step": ms32, "certified_bound": cert, "bound_iteration": total_iters,
-               "rel_err_vs_fp64_gpu": abs(cert - ref) / abs(ref),
-               "certified_below_fp64": bool(cert <= ref),
-               "speedup_vs_fp64": ms_per_step / ms32,
-               "iteration_hbm_fraction": 2.0 * nDs * 4 * (1000.0 / ms32) / 1e9 / HBM_PEAK_GBS}
-        h.close()
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    log(f"FP64 N={N}: {args.warmup} warm-up, {args.steps} step-launched, {extra} graph-launched iterations")
+    main_leg = timed_leg(F, D, "fp64", pair, args.warmup, args.steps, extra, stream)
+    it_s = 1000.0 / main_leg["ms_step"]
+    lb_trace = main_leg["lb_trace"]
+
+    legs = {}
+    for prec, key, skip in (("fp32", "fp32_certified", args.no_fp32), ("fp32n", "fp32_nearest", args.no_fp32)):
+        if skip:
+            continue
+        log(f"{prec} N={N}")
+        leg = timed_leg(F, D, prec, pair, args.warmup, args.steps, extra, stream)
+        legs[key] = leg_summary(leg, digest, ref_leg=main_leg)
+
     rel_err = rel_err_max = None
     gold = os.path.join(ROOT, "tests", "golden", f"clustered{N}_seed{args.seed}_oracle_lb.json")
     if os.path.exists(gold):
@@ -269,9 +353,11 @@ def main():
         rel_err_max = max(errs)
         if total_iters < m:
             rel_err = errs[total_iters]
-    bound = lb_trace[total_iters]
-    g.close()
+            for key in ("fp32_certified", "fp32_nearest"):
+                if key in legs:
+                    legs[key]["rel_err_vs_oracle"] = abs(legs[key]["bound"] - ref[total_iters]) / abs(ref[total_iters])
 
+    main_sum = leg_summary(main_leg, digest)
     out = {
         "metric": "RLT2 dual-ascent iters/s and LAPs/s at N=25; bound rel. error vs FP64",
         "value": it_s,
@@ -279,7 +365,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": main_leg["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -287,30 +373,62 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"clustered QAP N={N} seed {args.seed} (3-5 Gaussian clusters, "
                                f"70% sparse heavy-tailed flows), plain FP64 RLT2 dual ascent",
-                   "N": N, "laps_per_iteration": laps_per_iter, "D_entries": nD,
-                   "D_blocks": "one stored and concentrated per complementary pair" if pair else "all stored and concentrated",
+                   "N": N, "laps_per_iteration": laps_per_iteration(N, pair), "D_entries": sizes(N, pair)[1],
+                   "D_blocks": "one stored and concentrated per complementary pair" if pair
+                   else "all stored and concentrated",
                    "parallelism": "single GPU"},
-        "laps_per_s": laps_per_iter * it_s,
-        "bound": bound,
+        "laps_per_s": main_sum["laps_per_s"],
+        "bound": lb_trace[total_iters],
         "bound_rel_err_vs_oracle": rel_err,
         "bound_rel_err_vs_oracle_max_over_iterations": rel_err_max,
         "bound_iteration": total_iters,
-        "graph_iters_per_s": graph_it_s,
-        "iteration_hbm_fraction": iter_frac,
-        "kernel_ms": {names[s]: round(v, 4) for s, v in dur.items()},
-        "fp32_certified": f32,
-        "roofline": roofline(dom),
+        "graph_iters_per_s": main_sum["graph_iters_per_s"],
+        "graph_laps_per_s": main_sum["graph_laps_per_s"],
+        "iteration_hbm_fraction": main_sum["iteration_hbm_fraction"],
+        "kernel_ms": main_sum["kernel_ms"],
+        "roofline": main_sum["roofline"],
         # The cost sweep (steps 1-3) against the same peak: the step that
         # moves the whole cost array and is bound by HBM.
-        "roofline_sweep": roofline(3),
+        "roofline_sweep": main_sum["roofline_sweep"],
     }
+    out.update(legs)
+    if pair and not args.no_all_blocks:
+        log(f"FP64 N={N}, every block stored and concentrated")
+        leg = timed_leg(F, D, "fp64", False, args.warmup, args.steps, 0, stream)
+        s = leg_summary(leg, digest, with_rooflines=False)
+        s["laps_per_iteration"] = laps_per_iteration(N, False)
+        s["bound_matches_pair_path"] = bool(leg["lb_trace"][args.warmup + args.steps] ==
+                                            lb_trace[args.warmup + args.steps])
+        out["all_blocks"] = s
+    if not args.no_large:
+        F40, D40 = qapgen.clustered(40, 0)
+        large = {"workload": "clustered QAP N=40 seed 0, 20 iterations (1 warm-up, 19 step-launched)",
+                 "laps_per_iteration": laps_per_iteration(40, True)}
+        ref40 = None
+        for prec, key in (("fp64", "fp64"), ("fp32", "fp32_certified")):
+            log(f"{prec} N=40")
+            leg = timed_leg(F40, D40, prec, True, 1, 19, 0, stream)
+            large[key] = leg_summary(leg, digest, ref_leg=ref40)
+            if prec == "fp64":
+                ref40 = leg
+                large[key]["bound"] = leg["lb_trace"][20]
+        out["large_N40"] = large
     if not args.no_batched:
+        log("batched branch-and-bound nodes")
         out["batched"] = batched_leg(stream)
     if not args.no_cpu_baseline:
-        v, iters, cores = cpu_baseline(F, D, args.cpu_iters)
-        out["cpu_baseline"] = {"value": v, "unit": "iters/s", "cores": cores, "kind": "oracle",
-                               "sample": f"{iters} iterations (after iteration 0 and one untimed "
-                                         f"iteration) of the same N={N} instance, FP64"}
+        log("oracle on the host")
+        cb = cpu_baseline(F, D, args.cpu_iters)
+        out["cpu_baseline"] = {
+            "value": cb["all_cores"]["iters_per_s"], "unit": "iters/s", "cores": cb["all_cores"]["threads"],
+            "kind": "oracle",
+            "sample": f"{cb['all_cores']['iterations']} iterations (after iteration 0 and one untimed iteration) "
+                      f"of the same N={N} instance, FP64, on every core of the affinity set; single-threaded: "
+                      f"{cb['single_thread']['iterations']} iterations",
+            "single_thread_iters_per_s": cb["single_thread"]["iters_per_s"],
+            "model": cb["model"], "affinity_cores": cb["affinity_cores"],
+            "gpu_speedup_vs_all_cores": it_s / cb["all_cores"]["iters_per_s"],
+            "gpu_speedup_vs_single_thread": it_s / cb["single_thread"]["iters_per_s"]}
     print(json.dumps(out), flush=True)
 
 

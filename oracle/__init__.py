@@ -58,6 +58,8 @@ def _load():
     lib.oracle_rlt2_set_lb.restype = None
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
     _lib = lib
     return lib
 
@@ -73,6 +75,11 @@ def _iptr(a):
 def threads() -> int:
     """OpenMP threads the oracle runs with."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's parallel loops on n threads (results do not change)."""
+    _load().oracle_set_threads(int(n))
 
 
 def lap_solve(M):

@@ -26,6 +26,16 @@ int oracle_threads(void)
 #endif
 }
 
+/* Threads of the parallel loops that follow (results do not depend on it). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ========================================================================== */
 /* Linear assignment problem (Section 4.1: cost concentration is a LAP).       */
 /* ========================================================================== */

@@ -80,6 +80,8 @@ void    oracle_rlt2_set_lb(oracle_rlt2* s, double lb);
 
 /* Number of OpenMP threads the oracle runs with (1 when built without it). */
 int oracle_threads(void);
+/* Set the OpenMP thread count of the parallel loops (n >= 1). */
+void oracle_set_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -7,7 +7,8 @@ sizes and lengths.
 * N=25 clustered (100 iterations, the benchmark's workload): the bound of
   every iteration against the stored oracle trace and the live oracle, and
   every per-LAP value at iterations 10, 50 and 100, in FP64 (1e-9), FP32
-  round-to-nearest (1e-5) and FP32 certified (bound 1e-5).
+  round-to-nearest (1e-5 to iteration 50, 1e-4 at 100: see TOL32_LAP_N25)
+  and FP32 certified (bound 1e-5).
 * N=27 and N=35 (FP64 and FP32 round-to-nearest, 2 iterations): the large-N
   sweep kernel and the 64-lane / multi-column assignment classes, per-LAP
   values, B and C element by element.
@@ -114,6 +115,7 @@ def clustered25_oracle():
 
 
 def _trajectory(F, D, ref_lb, laps, precision, tol_lap):
+    """tol_lap: None, or {iteration: per-LAP tolerance} at the checkpoints."""
     g = Rlt2(F, D, precision=precision, trace_level=2, use_graph=True)
     done = 0
     worst = {}
@@ -121,12 +123,14 @@ def _trajectory(F, D, ref_lb, laps, precision, tol_lap):
         g.ascend(it - done)
         done = it
         sD, sC, _ = g.lap_values()
+        tol = tol_lap[it] if tol_lap is not None else 1.0
+        ok, err = layout.close_family(sD, laps[it][0], tol)
+        ok2, err2 = layout.close_family(sC, laps[it][1], tol)
+        print(f"{precision}: per-LAP rel err at iteration {it}: D->C {err:.3e}, C->B {err2:.3e}", flush=True)
+        worst[it] = max(err, err2)
         if tol_lap is not None:
-            ok, err = layout.close_family(sD, laps[it][0], tol_lap)
             assert ok, f"{precision}: D->C values at iteration {it}: {err}"
-            ok2, err2 = layout.close_family(sC, laps[it][1], tol_lap)
             assert ok2, f"{precision}: C->B values at iteration {it}: {err2}"
-            worst[it] = max(err, err2)
     lb, lbp = g.trace()
     assert len(lb) == 101
     assert (np.diff(lb) >= 0).all() and (lbp[1:] >= 0).all()
@@ -140,17 +144,27 @@ def test_clustered25_fp64_hundred_iterations(clustered25_oracle):
     F, D, ref_lb, laps = clustered25_oracle
     gold = json.load(open(os.path.join(ROOT, "tests", "golden", "clustered25_seed0_oracle_lb.json")))["lb"]
     np.testing.assert_array_equal(ref_lb, np.array(gold))   # the stored trace is the oracle's
-    lb, cert, worst = _trajectory(F, D, ref_lb, laps, "fp64", TOL64)
+    lb, cert, worst = _trajectory(F, D, ref_lb, laps, "fp64", {it: TOL64 for it in CHECK})
     rel = np.abs(lb - ref_lb) / ref_lb
     print(f"fp64: max bound rel err over 100 iterations {rel.max():.2e}; per-LAP {worst}", flush=True)
     assert rel.max() <= TOL64
     assert cert == lb[-1]
 
 
+# Per-LAP values of an FP32 state against the FP64 oracle at N=25: 1e-5 up to
+# iteration 50.  By iteration 100 the method itself has amplified the FP32
+# roundings past 1e-5 (measured on the oracle alone: one relative
+# perturbation of 3e-8 of C after iteration 0 moves per-LAP values by 5.7e-6
+# at iteration 100, and an FP32 state takes such a perturbation every
+# iteration), so the envelope there is 1e-4; the bound stays within 1e-5
+# throughout.
+TOL32_LAP_N25 = {10: TOL32, 50: TOL32, 100: 1e-4}
+
+
 @pytest.mark.timeout(900)
 def test_clustered25_fp32_nearest_hundred_iterations(clustered25_oracle):
     F, D, ref_lb, laps = clustered25_oracle
-    lb, cert, worst = _trajectory(F, D, ref_lb, laps, "fp32n", TOL32)
+    lb, cert, worst = _trajectory(F, D, ref_lb, laps, "fp32n", TOL32_LAP_N25)
     rel = np.abs(lb - ref_lb) / ref_lb
     print(f"fp32 nearest: max bound rel err {rel.max():.2e}; per-LAP {worst}", flush=True)
     assert rel.max() <= TOL32
