@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 legs (certified and nearest)")
     ap.add_argument("--no-all-blocks", action="store_true", help="skip the every-block FP64 leg")
     ap.add_argument("--no-large", action="store_true", help="skip the N=40 legs")
+    ap.add_argument("--no-solvers", action="store_true",
+                    help="skip the canonical-vs-auction assignment solver comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched branch-and-bound leg")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="oracle iterations in the CPU baseline (0: pick ~15 s of work)")
@@ -209,7 +211,7 @@ def laps_per_iteration(N, pair):
     return (nC // 2 if pair else nC) + N * N + 1
 
 
-def timed_leg(F, D, precision, pair, warmup, steps, graph_iters, stream):
+def timed_leg(F, D, precision, pair, warmup, steps, graph_iters, stream, lap_solver="canonical"):
     """One handle on the stream: `warmup` untimed iterations (the first runs
     the tuner), `steps` iterations launched step by step with HIP events
     around every step, then `graph_iters` iterations launched as one HIP graph
@@ -221,7 +223,7 @@ def timed_leg(F, D, precision, pair, warmup, steps, graph_iters, stream):
     N = F.shape[0]
     elem = 8 if precision == "fp64" else 4
     g = Rlt2(F, D, precision=precision, trace_level=1, use_graph=True, device=0, stream=stream.cuda_stream,
-             complementary=pair)
+             complementary=pair, lap_solver=lap_solver)
     if warmup:
         g.ascend(warmup)
     torch.cuda.synchronize()
@@ -260,6 +262,70 @@ def timed_leg(F, D, precision, pair, warmup, steps, graph_iters, stream):
     return {"N": N, "precision": precision, "pair": pair, "elem": elem, "ms_step": ms_step, "ms_graph": ms_graph,
             "dur": dur, "dom": dom, "bytes": bytes_, "lb_trace": lb_trace, "cert": cert,
             "iterations": warmup + steps + graph_iters}
+
+
+def solver_leg(F, D, stream, state_iters=10, reps=3):
+    """The two assignment solvers on the same live blocks: the stored D blocks
+    (n = N-2) of the N=25 state after `state_iters` iterations, solved as one
+    qap_lap_solve batch on device pointers with residuals written (the work of
+    one D->C concentration), by the canonical dual and by the auction."""
+    import numpy as np
+    import torch
+
+    from paper_1510_02065_amd import Rlt2, lap_solve_device
+    N = F.shape[0]
+    n = N - 2
+    g = Rlt2(F, D, device=0, stream=stream.cuda_stream)
+    g.ascend(state_iters)
+    _, _, _, Dst = g.read_state()
+    g.close()
+    nblk = N * N * (N - 1) * (N - 1)
+    blocks = Dst.reshape(nblk, n * n)
+    # one block of each complementary pair: (i, j, k, n) with i < k
+    idx = []
+    b = 0
+    for i in range(N):
+        for j in range(N):
+            for k in range(N):
+                if k == i:
+                    continue
+                for q in range(N):
+                    if q == j:
+                        continue
+                    if i < k:
+                        idx.append(b)
+                    b += 1
+    idx = np.array(idx)
+    dev = torch.device("cuda:0")
+    src = torch.tensor(blocks[idx].ravel(), dtype=torch.float64, device=dev)
+    cnt = len(idx)
+    nv = torch.full((cnt,), n, dtype=torch.int32, device=dev)
+    mo = torch.arange(cnt, dtype=torch.int64, device=dev) * (n * n)
+    value = torch.empty(cnt, dtype=torch.float64, device=dev)
+    out = {"workload": f"{cnt} stored D blocks (n={n}) of clustered N={N} seed 0 after {state_iters} iterations, "
+                       f"one qap_lap_solve call on device pointers with residuals written",
+           "problems": cnt}
+    vals = {}
+    for name, auction in (("canonical", False), ("auction", True)):
+        times = []
+        for _ in range(reps):
+            cost = src.clone()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            lap_solve_device(nv, mo, None, cost, value, residual=True, stream=stream, auction=auction)
+            e.record(stream)
+            e.synchronize()
+            times.append(a.elapsed_time(e))
+        ms = min(times)
+        vals[name] = value.cpu().numpy()
+        out[name] = {"ms": ms, "laps_per_s": cnt * 1000.0 / ms}
+    gap = (vals["canonical"] - vals["auction"]) / np.maximum(np.abs(vals["canonical"]), 1e-300)
+    out["auction"]["value_below_canonical_rel_max"] = float(gap.max())
+    out["auction"]["value_above_canonical_rel_max"] = float((-gap).max())
+    out["auction_speed_vs_canonical"] = out["canonical"]["ms"] / out["auction"]["ms"]
+    return out
 
 
 def roofline(leg, step, digest):
@@ -400,6 +466,15 @@ def main():
         s["bound_matches_pair_path"] = bool(leg["lb_trace"][args.warmup + args.steps] ==
                                             lb_trace[args.warmup + args.steps])
         out["all_blocks"] = s
+    if not args.no_solvers:
+        log(f"assignment solvers on the N={N} blocks; FP64 dual ascent with the auction solver")
+        sl = solver_leg(F, D, stream)
+        leg = timed_leg(F, D, "fp64", pair, args.warmup, args.steps, extra, stream, lap_solver="auction")
+        sl["dual_ascent"] = leg_summary(leg, digest, ref_leg=main_leg, with_rooflines=False)
+        if rel_err is not None:
+            ref = json.load(open(gold))["lb"]
+            sl["dual_ascent"]["bound_rel_to_oracle_canonical"] = leg["lb_trace"][total_iters] / ref[total_iters]
+        out["lap_solvers"] = sl
     if not args.no_large:
         F40, D40 = qapgen.clustered(40, 0)
         large = {"workload": "clustered QAP N=40 seed 0, 20 iterations (1 warm-up, 19 step-launched)",

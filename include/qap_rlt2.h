@@ -57,12 +57,15 @@ typedef enum {
 typedef enum {
     QAP_FP64 = 0,            /* all reduced costs and transfers in FP64         */
     QAP_FP32_CERTIFIED = 1,  /* FP32 reduced costs, every receiving write
-                                rounded toward -inf, FP64 bound and FP64
-                                certification (see qap_rlt2_certify): the
-                                stored state never represents more than the
-                                true objective, so the bound is proven valid;
-                                the directed roundings lower the trajectory
-                                by about one FP32 ulp per write               */
+                                at or below its exact value (rounded toward
+                                -inf, or computed in FP64 and lowered by a
+                                proven bound on its rounding error), FP64
+                                bound and FP64 certification (see
+                                qap_rlt2_certify): the stored state never
+                                represents more than the true objective, so
+                                the bound is proven valid; the trajectory
+                                drifts below FP64 by about one FP32 ulp per
+                                write                                         */
     QAP_FP32_NEAREST = 2     /* FP32 reduced costs, every receiving write
                                 computed in FP64 and rounded to nearest once,
                                 FP64 bound and FP64 certification: follows the
@@ -72,6 +75,20 @@ typedef enum {
                                 differs from the true one only by accumulated
                                 FP32 roundings                                */
 } qap_precision;
+
+/* Assignment solver of every cost concentration (Section 4.1). */
+typedef enum {
+    QAP_LAP_SOLVER_CANONICAL = 0, /* Hungarian method (shortest augmenting
+                                     paths), then the canonical optimal dual:
+                                     the mean of the column- and row-canonical
+                                     points, which does not depend on the
+                                     solver's path (the oracle's choice)     */
+    QAP_LAP_SOLVER_AUCTION = 1    /* auction algorithm with eps-scaling (the
+                                     solver of the paper's GPU code, Section
+                                     6), dual from the final prices: feasible,
+                                     within n * eps of optimal, so the bound is
+                                     valid, but the trajectory is its own     */
+} qap_lap_solver;
 
 typedef struct {
     int precision;    /* qap_precision                                        */
@@ -108,6 +125,7 @@ typedef struct {
                          1: the level-1 dual (B and C only, no D: an iteration
                          is steps 1, 5, 6, 7 and 8), the dual of the strong
                          branching of Section 6                              */
+    int lap_solver;    /* qap_lap_solver of the concentrations (default 0)    */
 } qap_rlt2_opts;
 
 typedef struct qap_rlt2 qap_rlt2;
@@ -262,12 +280,26 @@ qap_status qap_subproblem(int N, const double* F, const double* D, int m, const 
  *         column-canonical point (uc, vc) and row-canonical point (ur, vr).
  * assign  nullable; assign[r] = column given to row r by an optimal
  *         assignment (not unique when there are ties).
- * flags   QAP_LAP_DEVICE: every pointer above is device memory and the call
- *         is asynchronous on `stream`; otherwise all are host memory and the
+ * flags   QAP_LAP_DEVICE: every pointer above is device memory (of the
+ *         calling thread's current device) and the call is asynchronous on
+ *         `stream`; a device pass sorts the problems by size into a
+ *         workspace of 16 bytes per problem taken from the stream-ordered
+ *         allocator (hipMallocAsync) and released the same way.  Sizes
+ *         outside [0, 64] are not checked on the host: such a problem's
+ *         value is NaN and nothing else of it is written.  Otherwise all
+ *         pointers are host memory, sizes are checked (QAP_EINVAL) and the
  *         call is synchronous.  QAP_LAP_RESIDUAL: write residuals in place.
+ *         Problems of size n run in segments of the narrowest of 8, 16, 32
+ *         or 64 lanes that holds n, several problems per wave.
+ *         QAP_LAP_AUCTION: solve by the auction algorithm
+ *         (QAP_LAP_SOLVER_AUCTION); value is then the dual value of the final
+ *         prices (<= the optimum, within n * 2^-38 max|M| of it in FP64,
+ *         n * 2^-20 max|M| in FP32), duals are that point completed as for
+ *         the canonical one, and assign the auction's assignment.
  * stream  hipStream_t or NULL (the null stream). */
 #define QAP_LAP_DEVICE 1
 #define QAP_LAP_RESIDUAL 2
+#define QAP_LAP_AUCTION 4
 qap_status qap_lap_solve(int batch, const int32_t* n, const int64_t* mat_off,
                          const int64_t* vec_off, void* cost, int dtype,
                          double* value, void* duals, int32_t* assign,

@@ -17,7 +17,8 @@ QAP_FP64, QAP_FP32_CERTIFIED, QAP_FP32_NEAREST = 0, 1, 2
 # Precision names of the Python API: "fp32" is the certified mode (every
 # write rounded toward -inf), "fp32n" the round-to-nearest mode.
 PRECISIONS = {"fp64": QAP_FP64, "fp32": QAP_FP32_CERTIFIED, "fp32n": QAP_FP32_NEAREST}
-QAP_LAP_DEVICE, QAP_LAP_RESIDUAL = 1, 2
+QAP_LAP_DEVICE, QAP_LAP_RESIDUAL, QAP_LAP_AUCTION = 1, 2, 4
+SOLVERS = {"canonical": 0, "auction": 1}
 MAX_N = 64
 
 # Every function the header declares, with (restype, argtypes).
@@ -31,7 +32,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("trace_level", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("tune_cache", ctypes.c_char_p), ("complementary", ctypes.c_int), ("K", ctypes.c_double),
-                ("UB", ctypes.c_double), ("level", ctypes.c_int)]
+                ("UB", ctypes.c_double), ("level", ctypes.c_int), ("lap_solver", ctypes.c_int)]
 
 
 class BnbParams(ctypes.Structure):
@@ -137,13 +138,14 @@ def _dptr(a):
 
 
 def _opts(precision, trace_level, use_graph, device, stream, autotune=True, tune_cache=None,
-          complementary=True, K=0.0, UB=0.0, level=2):
+          complementary=True, K=0.0, UB=0.0, level=2, lap_solver="canonical"):
     opts = Opts()
     _check(lib().qap_rlt2_default_opts(ctypes.byref(opts)), "qap_rlt2_default_opts")
     opts.precision = PRECISIONS[precision]
     opts.K = float(K)
     opts.UB = float(UB)
     opts.level = int(level)
+    opts.lap_solver = SOLVERS[lap_solver]
     opts.device = device
     opts.stream = stream
     opts.trace_level = trace_level
@@ -161,7 +163,7 @@ class Rlt2:
 
     def __init__(self, F, D, B0=None, constant=0.0, precision="fp64", trace_level=1,
                  use_graph=True, device=-1, stream=None, autotune=True, tune_cache=None,
-                 complementary=True, K=0.0, UB=0.0, level=2):
+                 complementary=True, K=0.0, UB=0.0, level=2, lap_solver="canonical"):
         L = lib()
         F = _f64(F)
         D = _f64(D)
@@ -170,7 +172,7 @@ class Rlt2:
             raise ValueError("F and D must be square and of the same size")
         B0 = None if B0 is None else _f64(B0)
         opts = _opts(precision, trace_level, use_graph, device, stream, autotune, tune_cache, complementary,
-                     K, UB, level)
+                     K, UB, level, lap_solver)
         h = _vp()
         _check(L.qap_rlt2_create_ex(N, _dptr(F), _dptr(D), _dptr(B0), float(constant),
                                     ctypes.byref(opts), ctypes.byref(h)), "qap_rlt2_create_ex")
@@ -182,7 +184,7 @@ class Rlt2:
     @classmethod
     def batch(cls, Fs, Ds, B0s=None, constants=None, precision="fp64", trace_level=1,
               use_graph=True, device=-1, stream=None, autotune=True, tune_cache=None,
-              complementary=True, K=0.0, UB=0.0, level=2):
+              complementary=True, K=0.0, UB=0.0, level=2, lap_solver="canonical"):
         """Many instances (e.g. branch-and-bound nodes) in one handle."""
         count = len(Fs)
         Fs = [_f64(F) for F in Fs]
@@ -194,7 +196,7 @@ class Rlt2:
         dp = (ctypes.c_void_p * count)(*[D.ctypes.data for D in Ds])
         bp = (ctypes.c_void_p * count)(*[None if B is None else B.ctypes.data for B in B0s])
         opts = _opts(precision, trace_level, use_graph, device, stream, autotune, tune_cache, complementary,
-                     K, UB, level)
+                     K, UB, level, lap_solver)
         h = _vp()
         _check(lib().qap_rlt2_batch_create(count, Ns.ctypes.data, ctypes.cast(fp, _vp), ctypes.cast(dp, _vp),
                                            ctypes.cast(bp, _vp), consts.ctypes.data, ctypes.byref(opts),
@@ -442,8 +444,9 @@ def subproblem(F, D, fac, loc):
     return Fs, Ds, Bs, c.value
 
 
-def lap_solve(mats, residual=False, want_duals=True, want_assign=True):
-    """Solve a batch of square host matrices (list of 2-D arrays, FP64).
+def lap_solve(mats, residual=False, want_duals=True, want_assign=True, auction=False):
+    """Solve a batch of square host matrices (list of 2-D arrays, FP64);
+    auction=True: by the auction algorithm instead of the canonical dual.
 
     Returns dict with 'value' (S per problem), 'duals' (list of (4, n)
     arrays: uc, vc, ur, vr), 'assign' (list of row->column arrays) and, with
@@ -463,7 +466,7 @@ def lap_solve(mats, residual=False, want_duals=True, want_assign=True):
     value = np.empty(batch)
     duals = np.empty(4 * total_v) if want_duals else None
     assign = np.empty(total_v, dtype=np.int32) if want_assign else None
-    flags = QAP_LAP_RESIDUAL if residual else 0
+    flags = (QAP_LAP_RESIDUAL if residual else 0) | (QAP_LAP_AUCTION if auction else 0)
     _check(lib().qap_lap_solve(batch, n.ctypes.data, mat_off.ctypes.data, vec_off.ctypes.data,
                                cost.ctypes.data if total_m else None, QAP_FP64, value.ctypes.data,
                                None if duals is None else duals.ctypes.data,
@@ -480,11 +483,11 @@ def lap_solve(mats, residual=False, want_duals=True, want_assign=True):
 
 
 def lap_solve_device(n, mat_off, vec_off, cost, value, duals=None, assign=None, residual=False,
-                     stream=None, fp32=False, nearest=False):
+                     stream=None, fp32=False, nearest=False, auction=False):
     """Device-pointer batch: every argument is a torch CUDA tensor (or None);
     the call is asynchronous on `stream` (a torch.cuda.Stream or None)."""
     ptr = (lambda t: None if t is None else t.data_ptr())
-    flags = QAP_LAP_DEVICE | (QAP_LAP_RESIDUAL if residual else 0)
+    flags = QAP_LAP_DEVICE | (QAP_LAP_RESIDUAL if residual else 0) | (QAP_LAP_AUCTION if auction else 0)
     sp = None if stream is None else stream.cuda_stream
     _check(lib().qap_lap_solve(int(n.numel()), ptr(n), ptr(mat_off), ptr(vec_off), ptr(cost),
                                (QAP_FP32_NEAREST if nearest else QAP_FP32_CERTIFIED) if fp32 else QAP_FP64,

@@ -1,7 +1,8 @@
 """Build the qap_rlt2 HIP library for gfx950 in-tree (libqap_rlt2.so).
 
 hipcc cross-compiles the device code without a GPU.  The sources compile in
-parallel: the C ABI (api.hip), the launch code of each precision mode
+parallel: the C ABI (api.hip, and lap_solve.hip for the batched assignment
+solve), the launch code of each precision mode
 (ops_f64.hip, ops_f32d.hip, ops_f32n.hip) and the host-only branch and bound
 (bnb.cpp); then one link.  Flags:
   -ffp-contract=off   no fused multiply-add contraction, so the element-wise
@@ -20,7 +21,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqap_rlt2.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = [os.path.join(CSRC, f) for f in ("api.hip", "ops_f64.hip", "ops_f32d.hip", "ops_f32n.hip", "bnb.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("api.hip", "lap_solve.hip", "ops_f64.hip", "ops_f32d.hip", "ops_f32n.hip", "bnb.cpp")]
 HEADERS = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))] + [
     os.path.join(ROOT, "include", "qap_rlt2.h")]
 ARCH = os.environ.get("QAP_OFFLOAD_ARCH", "gfx950")

@@ -108,6 +108,10 @@ hipError_t enqueue_iteration(qap_rlt2* h)
 hipError_t tuned_first_iteration(qap_rlt2* h)
 {
     hipError_t e;
+    if (h->lap_solver == QAP_LAP_SOLVER_AUCTION) {   // one column per lane: nothing to tune
+        h->tuned = true;
+        return enqueue_iteration(h);
+    }
     if ((e = enqueue_step_any(h, 3)) != hipSuccess) return e;
     if (h->level == 2 && (e = QAP_OPS(h->precision, tune_family(h, qap::kFamD))) != hipSuccess) return e;
     if ((e = enqueue_step_any(h, 4)) != hipSuccess) return e;
@@ -207,6 +211,8 @@ qap_status make_handle(int count, const int32_t* Ns, const qap_rlt2_opts& o, qap
     if (o.precision != QAP_FP64 && o.precision != QAP_FP32_CERTIFIED && o.precision != QAP_FP32_NEAREST)
         return fail(QAP_EINVAL, "unknown precision");
     if (o.level != 1 && o.level != 2) return fail(QAP_EINVAL, "level must be 1 or 2");
+    if (o.lap_solver != QAP_LAP_SOLVER_CANONICAL && o.lap_solver != QAP_LAP_SOLVER_AUCTION)
+        return fail(QAP_EINVAL, "unknown lap_solver");
     if (!std::isfinite(o.K) || !std::isfinite(o.UB)) return fail(QAP_EINVAL, "non-finite K or UB");
 
     qap_rlt2* h = new (std::nothrow) qap_rlt2();
@@ -217,6 +223,7 @@ qap_status make_handle(int count, const int32_t* Ns, const qap_rlt2_opts& o, qap
     h->trace_level = std::max(0, std::min(2, o.trace_level));
     h->use_graph = o.use_graph ? 1 : 0;
     h->autotune = o.autotune ? 1 : 0;
+    h->lap_solver = o.lap_solver;
     if (o.tune_cache) h->tune_cache = o.tune_cache;
     h->dmode = o.complementary ? qap::kHalfStore : qap::kAllBlocks;
     h->elem = o.precision == QAP_FP64 ? sizeof(double) : sizeof(float);
@@ -533,6 +540,7 @@ qap_status qap_rlt2_default_opts(qap_rlt2_opts* o)
     o->K = 0.0;
     o->UB = 0.0;
     o->level = 2;
+    o->lap_solver = QAP_LAP_SOLVER_CANONICAL;
     return QAP_OK;
 }
 
@@ -1139,6 +1147,7 @@ qap_status qap_rlt2_children(qap_rlt2* h, int k, int count, const int32_t* fac, 
     o.K = h->stopK;
     o.UB = h->stopUB;
     o.level = level;
+    o.lap_solver = h->lap_solver;
     std::vector<int32_t> Ns(count, N - 1);
     qap_rlt2* c = nullptr;
     if ((st = make_handle(count, Ns.data(), o, &c)) != QAP_OK) return st;
@@ -1269,103 +1278,6 @@ qap_status qap_subproblem(int N, const double* F, const double* D, int m, const 
     for (int t = 0; t < m; ++t)
         for (int u = 0; u < m; ++u) c += F[fac[t] * N + fac[u]] * D[loc[t] * N + loc[u]];
     *constant = c;
-    return QAP_OK;
-}
-
-qap_status qap_lap_solve(int batch, const int32_t* n, const int64_t* mat_off, const int64_t* vec_off, void* cost,
-                         int dtype, double* value, void* duals, int32_t* assign, int flags, void* stream)
-{
-    qap::last_error().clear();
-    if (batch < 0) return fail(QAP_EINVAL, "negative batch");
-    if (batch == 0) return QAP_OK;
-    if (!n || !mat_off || !cost || !value) return fail(QAP_EINVAL, "null n, mat_off, cost or value");
-    if ((duals || assign) && !vec_off) return fail(QAP_EINVAL, "vec_off needed for duals or assign");
-    if (dtype != QAP_FP64 && dtype != QAP_FP32_CERTIFIED && dtype != QAP_FP32_NEAREST)
-        return fail(QAP_EINVAL, "unknown dtype");
-    const size_t es = dtype == QAP_FP64 ? sizeof(double) : sizeof(float);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const int wr = (flags & QAP_LAP_RESIDUAL) ? 1 : 0;
-    if (flags & QAP_LAP_DEVICE) {
-        QAP_HIP(QAP_OPS(dtype, lap_batch(st, 64, batch, nullptr, nullptr, n, mat_off, vec_off, cost, value, duals,
-                                         assign, wr)));
-        return QAP_OK;
-    }
-    // Host pointers: validate, bucket by size, stage, solve, copy back.
-    int64_t mat_end = 0, vec_end = 0;
-    std::vector<int32_t> order[4];   // problems of each segment class (8, 16, 32, 64 lanes)
-    for (int b = 0; b < batch; ++b) {
-        if (n[b] < 0 || n[b] > QAP_RLT2_MAX_N) return fail(QAP_EINVAL, "n[b] must be in [0, 64]");
-        if (mat_off[b] < 0) return fail(QAP_EINVAL, "negative mat_off");
-        mat_end = std::max(mat_end, mat_off[b] + (int64_t)n[b] * n[b]);
-        for (int64_t e = 0; e < (int64_t)n[b] * n[b]; ++e) {
-            const double x = dtype == QAP_FP64 ? static_cast<const double*>(cost)[mat_off[b] + e]
-                                               : (double)static_cast<const float*>(cost)[mat_off[b] + e];
-            if (!std::isfinite(x)) return fail(QAP_EINVAL, "non-finite cost entry");
-        }
-        if (vec_off) {
-            if (vec_off[b] < 0) return fail(QAP_EINVAL, "negative vec_off");
-            vec_end = std::max(vec_end, vec_off[b] + (int64_t)n[b]);
-        }
-        const int seg = qap::seg_for(std::max<int>(n[b], 1));
-        order[seg == 8 ? 0 : seg == 16 ? 1 : seg == 32 ? 2 : 3].push_back(b);
-    }
-    std::vector<int32_t> idx;
-    for (auto& o : order) idx.insert(idx.end(), o.begin(), o.end());
-    int32_t *dn = nullptr, *didx = nullptr;
-    int64_t *dmo = nullptr, *dvo = nullptr;
-    void *dcost = nullptr, *ddual = nullptr;
-    double* dval = nullptr;
-    int32_t* dassign = nullptr;
-    qap_status result = QAP_OK;
-    auto cleanup = [&]() {
-        for (void* p : {(void*)dn, (void*)didx, (void*)dmo, (void*)dvo, (void*)dcost, (void*)dval, (void*)ddual,
-                        (void*)dassign})
-            if (p) (void)hipFree(p);
-    };
-#define CK2(call)                                                                                    \
-    do {                                                                                             \
-        hipError_t e_ = (call);                                                                      \
-        if (e_ != hipSuccess) {                                                                      \
-            result = fail(e_ == hipErrorOutOfMemory ? QAP_ENOMEM : QAP_EDEVICE,                      \
-                          std::string(#call) + ": " + hipGetErrorString(e_));                        \
-            cleanup();                                                                               \
-            return result;                                                                           \
-        }                                                                                            \
-    } while (0)
-    CK2(hipMalloc(&dn, batch * sizeof(int32_t)));
-    CK2(hipMalloc(&didx, batch * sizeof(int32_t)));
-    CK2(hipMalloc(&dmo, batch * sizeof(int64_t)));
-    CK2(hipMalloc(&dcost, std::max<int64_t>(mat_end, 1) * es));
-    CK2(hipMalloc(&dval, batch * sizeof(double)));
-    CK2(hipMemcpyAsync(dn, n, batch * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    CK2(hipMemcpyAsync(didx, idx.data(), batch * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    CK2(hipMemcpyAsync(dmo, mat_off, batch * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    if (mat_end > 0) CK2(hipMemcpyAsync(dcost, cost, mat_end * es, hipMemcpyHostToDevice, st));
-    if (vec_off) {
-        CK2(hipMalloc(&dvo, batch * sizeof(int64_t)));
-        CK2(hipMemcpyAsync(dvo, vec_off, batch * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    }
-    if (duals) CK2(hipMalloc(&ddual, std::max<int64_t>(4 * vec_end, 1) * es));
-    if (assign) CK2(hipMalloc(&dassign, std::max<int64_t>(vec_end, 1) * sizeof(int32_t)));
-    // One launch per size class: a problem of size n runs in a segment of the
-    // smallest width that holds it, so small problems share a wave.
-    int64_t first = 0;
-    const int segs[4] = {8, 16, 32, 64};
-    for (int c = 0; c < 4; ++c) {
-        const int cnt = (int)order[c].size();
-        if (cnt > 0)
-            CK2(QAP_OPS(dtype, lap_batch(st, segs[c], cnt, nullptr, didx + first, dn, dmo, dvo, dcost, dval, ddual,
-                                         dassign, wr)));
-        first += cnt;
-    }
-    CK2(hipMemcpyAsync(value, dval, batch * sizeof(double), hipMemcpyDeviceToHost, st));
-    if (wr && mat_end > 0) CK2(hipMemcpyAsync(cost, dcost, mat_end * es, hipMemcpyDeviceToHost, st));
-    if (duals && vec_end > 0) CK2(hipMemcpyAsync(duals, ddual, 4 * vec_end * es, hipMemcpyDeviceToHost, st));
-    if (assign && vec_end > 0)
-        CK2(hipMemcpyAsync(assign, dassign, vec_end * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    CK2(hipStreamSynchronize(st));
-#undef CK2
-    cleanup();
     return QAP_OK;
 }
 

@@ -114,6 +114,7 @@ struct qap_rlt2 {
     int trace_level = 1;
     int use_graph = 1;
     int autotune = 1;
+    int lap_solver = QAP_LAP_SOLVER_CANONICAL;   // qap_lap_solver of the concentrations
     long long pending = 0;   // iterations of qap_rlt2_step whose trace entries are still on the device
     int dmode = qap::kHalfStore;   // D storage and enumeration (kAllBlocks or kHalfStore)
     int Nmax = 0;                  // largest instance
@@ -178,10 +179,11 @@ struct Ops {
     static size_t sweep_lds(int N);
     // Batched assignment problems (qap_lap_solve) with `seg` lanes per
     // problem: slot s < count (count = *dcount if dcount is not null, the
-    // grid sized for `count`) solves problem idx[s] (s if idx is null).
+    // grid sized for `count`) solves problem idx[s] (s if idx is null), by
+    // the canonical dual or the auction (solver, a qap_lap_solver value).
     static hipError_t lap_batch(hipStream_t st, int seg, int count, const int* dcount, const int32_t* idx,
                                 const int32_t* n, const int64_t* mo, const int64_t* vo, void* cost, double* value,
-                                void* duals, int32_t* assign, int wr);
+                                void* duals, int32_t* assign, int wr, int solver);
     // Children of parent instance pk of handle ph (fixings fix[2c], fix[2c+1]
     // in device memory) into handle ch, whose instances are those children.
     static hipError_t inherit(qap_rlt2* ph, int pk, qap_rlt2* ch, const int* dfix);

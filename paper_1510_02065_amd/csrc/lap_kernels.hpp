@@ -4,6 +4,7 @@
 // waves.  Problems of every instance of a handle are served by one launch per
 // segment-size class.
 #pragma once
+#include "lap_auction.hpp"
 #include "lap_slots.hpp"
 #include "lap_wave.hpp"
 
@@ -72,8 +73,9 @@ __device__ __forceinline__ void stage_block(T* __restrict__ M, const T* __restri
 // (kFamC: blocks C_ij of size N-1, parent b_ij), K columns per lane, 64/SEG
 // problems per wave, one wave per workgroup.  parent += S, the block is
 // replaced by its residual, values[...] = S when values is not null (values
-// are packed like the parents).  `mode` applies to the D family only.
-template <int PM, int SEG, int K, int FAM>
+// are packed like the parents).  `mode` applies to the D family only.  AUC:
+// the auction solver (one column per lane only).
+template <int PM, int SEG, int K, int FAM, bool AUC = false>
 __global__ __launch_bounds__(64) void k_lap_family_s(StoreT<PM>* __restrict__ D, StoreT<PM>* __restrict__ C,
                                                      StoreT<PM>* __restrict__ B, const Inst* __restrict__ inst,
                                                      FamilyClass fc, int nmax, double* __restrict__ values, int mode,
@@ -121,7 +123,10 @@ __global__ __launch_bounds__(64) void k_lap_family_s(StoreT<PM>* __restrict__ D,
     stage_block<T, SEG, K>(sc.M, blk, ld, n, lane);
     wave_sync();
     double S;
-    if constexpr (K == 1)
+    static_assert(!AUC || K == 1, "the auction solver takes one column per lane");
+    if constexpr (AUC)
+        S = lap_auction_flat<T, SEG, DOWN>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
+    else if constexpr (K == 1)
         S = lap_concentrate_flat<T, SEG, DOWN>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
     else
         S = lap_concentrate_slots<T, SEG, K, DOWN>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
@@ -144,7 +149,7 @@ __global__ __launch_bounds__(64) void k_lap_family_s(StoreT<PM>* __restrict__ D,
 // permutation of the instance.  Stop rule of Algorithm 1, with stop[0] = K and
 // stop[1] = UB (UB <= 0: none): the instance's act flag is cleared once
 // LB >= UB or LB' / UB < K.
-template <int PM, int SEG, int K>
+template <int PM, int SEG, int K, bool AUC = false>
 __global__ __launch_bounds__(64) void k_lap_B_s(StoreT<PM>* __restrict__ B, const Inst* __restrict__ inst,
                                                 FamilyClass fc, int nmax, double* __restrict__ lb,
                                                 double* __restrict__ trace, long long* __restrict__ counter,
@@ -169,7 +174,10 @@ __global__ __launch_bounds__(64) void k_lap_B_s(StoreT<PM>* __restrict__ B, cons
     wave_sync();
     int32_t* sg = (active && sigma) ? sigma + I.offB : nullptr;
     double S;
-    if constexpr (K == 1)
+    static_assert(!AUC || K == 1, "the auction solver takes one column per lane");
+    if constexpr (AUC)
+        S = lap_auction_flat<T, SEG, DOWN>(sc, n, active ? blk : nullptr, n, nullptr, sg);
+    else if constexpr (K == 1)
         S = lap_concentrate_flat<T, SEG, DOWN>(sc, n, active ? blk : nullptr, n, nullptr, sg);
     else
         S = lap_concentrate_slots<T, SEG, K, DOWN>(sc, n, active ? blk : nullptr, n, nullptr, sg);
@@ -195,8 +203,9 @@ __global__ __launch_bounds__(64) void k_lap_B_s(StoreT<PM>* __restrict__ B, cons
 // b = idx[s] (b = s when idx is null); count = *dcount when dcount is not
 // null, else `count`.  Problem b has size n[b] (<= SEG, else its value is NaN
 // and nothing else is written), matrix at cost + mat_off[b], vectors at
-// vec_off[b] (vec_off may be null when duals and assign are).
-template <int PM, int SEG>
+// vec_off[b] (vec_off may be null when duals and assign are).  AUC: the
+// auction solver (lap_auction_flat) instead of the canonical dual.
+template <int PM, int SEG, bool AUC>
 __global__ __launch_bounds__(64) void k_lap_batch(int count, const int* __restrict__ dcount,
                                                   const int32_t* __restrict__ idx, const int32_t* __restrict__ nv,
                                                   const int64_t* __restrict__ mat_off,
@@ -222,9 +231,14 @@ __global__ __launch_bounds__(64) void k_lap_batch(int count, const int* __restri
     const int64_t vo = (in && !bad && vec_off) ? vec_off[b] : 0;
     stage_block<T, SEG, 1>(sc.M, mat, n, n, lane);
     wave_sync();
-    const double S = lap_concentrate_flat<T, SEG, PM == kPrecF32Down>(
-        sc, n, (write_residual && n > 0) ? mat : nullptr, n, (duals && n > 0) ? duals + 4 * vo : nullptr,
-        (assign && n > 0) ? assign + vo : nullptr);
+    T* const Rw = (write_residual && n > 0) ? mat : nullptr;
+    T* const dw = (duals && n > 0) ? duals + 4 * vo : nullptr;
+    int32_t* const aw = (assign && n > 0) ? assign + vo : nullptr;
+    double S;
+    if constexpr (AUC)
+        S = lap_auction_flat<T, SEG, PM == kPrecF32Down>(sc, n, Rw, n, dw, aw);
+    else
+        S = lap_concentrate_flat<T, SEG, PM == kPrecF32Down>(sc, n, Rw, n, dw, aw);
     // A quiet NaN written by bit pattern marks a problem that was not solved.
     if (in && lane == 0) value[b] = bad ? __longlong_as_double(0x7ff8000000000000ll) : S;
 }

@@ -361,11 +361,24 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
         wave_sync();
         return 0.5 * ((suc + svc) + (sur + svr));
     } else {
-        // ---- FP32 certified: the duals are completed in FP64 rounding toward
-        // -inf, which keeps them feasible (u_r + v_q <= M_rq exactly).  With
-        // U = (uc + ur)/2 and V = (vc + vr)/2 the residual M - U - V (the same
-        // value as the mean of the two residuals) is then >= 0, and each entry
-        // and S = sum U + sum V are rounded down once.
+        // ---- FP32 certified: the duals are completed in FP64 so that they
+        // stay feasible (u_r + v_q <= M_rq exactly).  With U = (uc + ur)/2
+        // and V = (vc + vr)/2 the residual M - U - V (the same value as the
+        // mean of the two residuals) is then >= 0, and each entry and
+        // S = sum U + sum V are written rounded down.
+        //
+        // A completed dual is a minimum of differences t = M - d.  Each
+        // difference is computed once in round-to-nearest FP64, within
+        // 2^-53 |t| of the exact one; as t - 2^-53 |t| increases with t, the
+        // minimum m of the computed differences lowered by 2^-50 |m| (the
+        // lowering itself rounding by at most 2^-53 of the result) lies below
+        // every exact difference.  A residual entry M - V - U is computed in
+        // two round-to-nearest steps, within 2.01 * 2^-53 (|M| + |V| + |U|)
+        // of the exact value; lowered by 2^-50 times that sum (the lowering's
+        // own rounding included), then by the float conversion toward -inf,
+        // and clamped at 0 (the exact residual is >= 0), it is a valid lower
+        // value.  Both replace per-operation directed rounding (TwoSum) with
+        // a margin far below one FP32 step.
         for (int s = 0; s < K; ++s) {
             if (!ok[s]) continue;
             sc.u[c[s]] = (double)vc[s];
@@ -378,9 +391,11 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             vr[s] = __builtin_huge_val();
             if (ok[s]) {
                 for (int q = 0; q < n; ++q)
-                    uc[s] = __builtin_fmin(uc[s], sub_down((double)M[c[s] * n + q], sc.u[q]));
+                    uc[s] = __builtin_fmin(uc[s], (double)M[c[s] * n + q] - sc.u[q]);
                 for (int r = 0; r < n; ++r)
-                    vr[s] = __builtin_fmin(vr[s], sub_down((double)M[r * n + c[s]], sc.vb[r]));
+                    vr[s] = __builtin_fmin(vr[s], (double)M[r * n + c[s]] - sc.vb[r]);
+                uc[s] -= __builtin_fabs(uc[s]) * 0x1p-50;
+                vr[s] -= __builtin_fabs(vr[s]) * 0x1p-50;
             }
             U[s] = ok[s] ? 0.5 * add_down(uc[s], (double)ur[s]) : 0.0;   // lane as rows
             V[s] = ok[s] ? 0.5 * add_down((double)vc[s], vr[s]) : 0.0;   // lane as columns
@@ -393,8 +408,13 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             for (int s = 0; s < K; ++s) {
                 if (!ok[s]) continue;
                 T* Rr = R + c[s];
-                for (int r = 0; r < n; ++r, Rr += ldr)
-                    *Rr = to_float_down(sub_down(sub_down((double)M[r * n + c[s]], V[s]), sc.u[r]));
+                for (int r = 0; r < n; ++r, Rr += ldr) {
+                    const double m = (double)M[r * n + c[s]];
+                    const double ur_ = sc.u[r];
+                    const double t = (m - V[s]) - ur_;
+                    const double margin = ((__builtin_fabs(m) + __builtin_fabs(V[s])) + __builtin_fabs(ur_)) * 0x1p-50;
+                    *Rr = to_float_down(__builtin_fmax(t - margin, 0.0));
+                }
             }
         }
         for (int s = 0; s < K; ++s) {

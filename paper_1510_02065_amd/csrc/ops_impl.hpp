@@ -11,7 +11,7 @@ namespace qap {
 
 namespace {
 
-template <int PM, int SEG, int K>
+template <int PM, int SEG, int K, bool AUC = false>
 hipError_t launch_family_sk(qap_rlt2* h, int famk, const ClassHost& c, FamilyClass fc, double* values, int mode)
 {
     using T = StoreT<PM>;
@@ -24,11 +24,11 @@ hipError_t launch_family_sk(qap_rlt2* h, int famk, const ClassHost& c, FamilyCla
     T* C = static_cast<T*>(h->dC);
     T* B = static_cast<T*>(h->dB);
     if (famk == kFamD)
-        hipLaunchKernelGGL((k_lap_family_s<PM, SEG, K, kFamD>), dim3(grid), dim3(64), lds, h->stream, D, C, B,
-                           h->dInst, fc, c.nmax, values, mode, h->dAct);
+        hipLaunchKernelGGL((k_lap_family_s<PM, SEG, K, kFamD, AUC>), dim3(grid), dim3(64), lds, h->stream, D, C,
+                           B, h->dInst, fc, c.nmax, values, mode, h->dAct);
     else
-        hipLaunchKernelGGL((k_lap_family_s<PM, SEG, K, kFamC>), dim3(grid), dim3(64), lds, h->stream, D, C, B,
-                           h->dInst, fc, c.nmax, values, kAllBlocks, h->dAct);
+        hipLaunchKernelGGL((k_lap_family_s<PM, SEG, K, kFamC, AUC>), dim3(grid), dim3(64), lds, h->stream, D, C,
+                           B, h->dInst, fc, c.nmax, values, kAllBlocks, h->dAct);
     return hipGetLastError();
 }
 
@@ -44,18 +44,33 @@ hipError_t launch_family_class(qap_rlt2* h, int famk, const ClassHost& c, Family
     return hipErrorInvalidConfiguration;
 }
 
+// The auction solver's launch for a size class: one column per lane, in the
+// class's own segment width.
+template <int PM>
+hipError_t launch_family_auction(qap_rlt2* h, int famk, const ClassHost& c, double* values, int mode)
+{
+    switch (c.seg) {
+    case 8: return launch_family_sk<PM, 8, 1, true>(h, famk, c, c.dev(), values, mode);
+    case 16: return launch_family_sk<PM, 16, 1, true>(h, famk, c, c.dev(), values, mode);
+    case 32: return launch_family_sk<PM, 32, 1, true>(h, famk, c, c.dev(), values, mode);
+    default: return launch_family_sk<PM, 64, 1, true>(h, famk, c, c.dev(), values, mode);
+    }
+}
+
 template <int PM>
 hipError_t launch_family(qap_rlt2* h, int famk, double* values)
 {
     for (const ClassHost& c : h->fam[famk]) {
         if (c.total <= 0) continue;
-        hipError_t e = launch_family_class<PM>(h, famk, c, c.dev(), c.seg_run, c.k_run, values, h->dmode);
+        hipError_t e = h->lap_solver == QAP_LAP_SOLVER_AUCTION
+                           ? launch_family_auction<PM>(h, famk, c, values, h->dmode)
+                           : launch_family_class<PM>(h, famk, c, c.dev(), c.seg_run, c.k_run, values, h->dmode);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-template <int PM, int SEG, int K>
+template <int PM, int SEG, int K, bool AUC = false>
 hipError_t launch_B_sk(qap_rlt2* h, const ClassHost& c)
 {
     using T = StoreT<PM>;
@@ -64,7 +79,7 @@ hipError_t launch_B_sk(qap_rlt2* h, const ClassHost& c)
     if (lds > h->lds_limit) return hipErrorInvalidConfiguration;
     const unsigned grid = (unsigned)((c.total + LPW - 1) / LPW);
     const bool tr = h->trace_level >= 1;
-    hipLaunchKernelGGL((k_lap_B_s<PM, SEG, K>), dim3(grid), dim3(64), lds, h->stream, static_cast<T*>(h->dB),
+    hipLaunchKernelGGL((k_lap_B_s<PM, SEG, K, AUC>), dim3(grid), dim3(64), lds, h->stream, static_cast<T*>(h->dB),
                        h->dInst, c.dev(), c.nmax, h->dLB, tr ? h->dTrace : nullptr, h->dCounter, kTraceCap,
                        h->trace_level >= 2 ? h->dValB : nullptr, h->dSigma, h->dAct, h->dStop);
     return hipGetLastError();
@@ -78,7 +93,11 @@ hipError_t launch_B(qap_rlt2* h)
         hipError_t e = hipErrorInvalidConfiguration;
 #define QAP_CFG(SG, KK) \
     else if (c.seg_run == SG && c.k_run == KK) e = launch_B_sk<PM, SG, KK>(h, c);
-        if (false) {
+        if (h->lap_solver == QAP_LAP_SOLVER_AUCTION) {
+            e = c.seg == 8    ? launch_B_sk<PM, 8, 1, true>(h, c)
+                : c.seg == 16 ? launch_B_sk<PM, 16, 1, true>(h, c)
+                : c.seg == 32 ? launch_B_sk<PM, 32, 1, true>(h, c)
+                              : launch_B_sk<PM, 64, 1, true>(h, c);
         }
         QAP_CFG(8, 1) QAP_CFG(8, 2) QAP_CFG(8, 3) QAP_CFG(8, 4) QAP_CFG(8, 5) QAP_CFG(8, 6) QAP_CFG(8, 8)
         QAP_CFG(16, 1) QAP_CFG(16, 2) QAP_CFG(16, 3) QAP_CFG(16, 4) QAP_CFG(32, 1) QAP_CFG(32, 2) QAP_CFG(64, 1)
@@ -88,7 +107,7 @@ hipError_t launch_B(qap_rlt2* h)
     return hipSuccess;
 }
 
-template <int PM, int SEG>
+template <int PM, int SEG, bool AUC>
 hipError_t launch_batch_seg(hipStream_t st, int count, const int* dcount, const int32_t* idx, const int32_t* n,
                             const int64_t* mo, const int64_t* vo, StoreT<PM>* cost, double* value,
                             StoreT<PM>* duals, int32_t* assign, int wr)
@@ -98,7 +117,7 @@ hipError_t launch_batch_seg(hipStream_t st, int count, const int* dcount, const 
     constexpr int LPW = 64 / SEG;
     const size_t lds = LPW * SlotLds<T, SEG, 1>::bytes(SEG);
     const unsigned grid = (unsigned)((count + LPW - 1) / LPW);
-    hipLaunchKernelGGL((k_lap_batch<PM, SEG>), dim3(grid), dim3(64), lds, st, count, dcount, idx, n, mo, vo, cost,
+    hipLaunchKernelGGL((k_lap_batch<PM, SEG, AUC>), dim3(grid), dim3(64), lds, st, count, dcount, idx, n, mo, vo, cost,
                        value, duals, assign, wr);
     return hipGetLastError();
 }
@@ -279,17 +298,22 @@ hipError_t Ops<PM>::init_instance(qap_rlt2* h, int k, const double* dF, const do
 template <int PM>
 hipError_t Ops<PM>::lap_batch(hipStream_t st, int seg, int count, const int* dcount, const int32_t* idx,
                               const int32_t* n, const int64_t* mo, const int64_t* vo, void* cost, double* value,
-                              void* duals, int32_t* assign, int wr)
+                              void* duals, int32_t* assign, int wr, int solver)
 {
     using T = StoreT<PM>;
     T* c = static_cast<T*>(cost);
     T* d = static_cast<T*>(duals);
+#define QAP_SEG(SG)                                                                                            \
+    return solver == QAP_LAP_SOLVER_AUCTION                                                                    \
+               ? launch_batch_seg<PM, SG, true>(st, count, dcount, idx, n, mo, vo, c, value, d, assign, wr)  \
+               : launch_batch_seg<PM, SG, false>(st, count, dcount, idx, n, mo, vo, c, value, d, assign, wr)
     switch (seg) {
-    case 8: return launch_batch_seg<PM, 8>(st, count, dcount, idx, n, mo, vo, c, value, d, assign, wr);
-    case 16: return launch_batch_seg<PM, 16>(st, count, dcount, idx, n, mo, vo, c, value, d, assign, wr);
-    case 32: return launch_batch_seg<PM, 32>(st, count, dcount, idx, n, mo, vo, c, value, d, assign, wr);
-    default: return launch_batch_seg<PM, 64>(st, count, dcount, idx, n, mo, vo, c, value, d, assign, wr);
+    case 8: QAP_SEG(8);
+    case 16: QAP_SEG(16);
+    case 32: QAP_SEG(32);
+    default: QAP_SEG(64);
     }
+#undef QAP_SEG
 }
 
 template <int PM>

@@ -101,6 +101,44 @@ __device__ __forceinline__ float add_down_to_float(double a, double b) {
     return f;
 }
 
+// Mean of the six member sums (d_m + x_m), m = 0..5, of one six-way group,
+// rounded toward -inf, for the FP32 certified mode (the terms are the stored
+// members and their spread shares, as floats).  When every term is >= 0 the
+// round-to-nearest FP64 sum (m_0 + ... + m_5, each m = d + x) is within
+// (1 + 2^-53)^6 - 1 < 7 * 2^-53 of the exact sum, relatively; multiplying by
+// 1/6 (two more roundings) and by 1 - 2^-48 therefore gives a value below the
+// exact mean, and its largest float below is written.  That is at most one
+// FP32 step below the directed result, for a fraction of the work of
+// rounding every step toward -inf, which is what happens when a term is
+// negative (a state loaded by the caller may hold such entries).
+__device__ __forceinline__ float mean6_down(float d0, float x0, float d1, float x1, float d2, float x2, float d3,
+                                            float x3, float d4, float x4, float d5, float x5)
+{
+    const float lo = fminf(fminf(fminf(fminf(d0, x0), fminf(d1, x1)), fminf(fminf(d2, x2), fminf(d3, x3))),
+                           fminf(fminf(d4, x4), fminf(d5, x5)));
+    if (lo >= 0.0f) {
+        double sum = (double)d0 + (double)x0;
+        sum += (double)d1 + (double)x1;
+        sum += (double)d2 + (double)x2;
+        sum += (double)d3 + (double)x3;
+        sum += (double)d4 + (double)x4;
+        sum += (double)d5 + (double)x5;
+        return to_float_down((sum * (1.0 / 6.0)) * (1.0 - 0x1p-48));
+    }
+    double sum = add_down((double)d0, (double)x0);
+    sum = add_down(sum, (double)d1);
+    sum = add_down(sum, (double)x1);
+    sum = add_down(sum, (double)d2);
+    sum = add_down(sum, (double)x2);
+    sum = add_down(sum, (double)d3);
+    sum = add_down(sum, (double)x3);
+    sum = add_down(sum, (double)d4);
+    sum = add_down(sum, (double)x4);
+    sum = add_down(sum, (double)d5);
+    sum = add_down(sum, (double)x5);
+    return to_float_down(div_down(sum, 6.0));
+}
+
 // Precision modes (the values of qap_precision).  kPrecF64: FP64 state,
 // round-to-nearest.  kPrecF32Down: FP32 state, every value written rounded
 // toward -inf once (the represented objective can only fall, a proof of
@@ -414,18 +452,8 @@ __global__ __launch_bounds__(256) void k_sweep(StoreT<PM>* __restrict__ Dd, cons
         s += m5;
         mean = (T)(s / 6.0);
     } else {
-        double s = add_down((double)Dk[a0], (double)CCk[b0]);
-        s = add_down(s, (double)Dk[a1]);
-        s = add_down(s, (double)CCk[b1]);
-        s = add_down(s, (double)Dk[a2]);
-        s = add_down(s, (double)CCk[b2]);
-        s = add_down(s, (double)Dk[a3]);
-        s = add_down(s, (double)CCk[b3]);
-        s = add_down(s, (double)Dk[a4]);
-        s = add_down(s, (double)CCk[b4]);
-        s = add_down(s, (double)Dk[a5]);
-        s = add_down(s, (double)CCk[b5]);
-        mean = to_float_down(div_down(s, 6.0));
+        mean = mean6_down(Dk[a0], CCk[b0], Dk[a1], CCk[b1], Dk[a2], CCk[b2], Dk[a3], CCk[b3], Dk[a4], CCk[b4],
+                          Dk[a5], CCk[b5]);
     }
     Dk[a0] = mean;
     Dk[a1] = mean;
@@ -475,18 +503,7 @@ __device__ __forceinline__ T six_way_mean(T A0, T B0, T C0, T x0, T x1, T x2, T 
         sum += m5;
         return (T)(sum / 6.0);
     } else {
-        double sum = add_down((double)A0, (double)x0);
-        sum = add_down(sum, (double)B0);
-        sum = add_down(sum, (double)x1);
-        sum = add_down(sum, (double)A0);
-        sum = add_down(sum, (double)x2);
-        sum = add_down(sum, (double)C0);
-        sum = add_down(sum, (double)x3);
-        sum = add_down(sum, (double)B0);
-        sum = add_down(sum, (double)x4);
-        sum = add_down(sum, (double)C0);
-        sum = add_down(sum, (double)x5);
-        return to_float_down(div_down(sum, 6.0));
+        return mean6_down(A0, x0, B0, x1, A0, x2, C0, x3, B0, x4, C0, x5);
     }
 }
 

@@ -80,11 +80,12 @@ def test_every_registered_kernel_has_device_code(libpath, tmp_path):
         # whose length is part of the mangled identifier: rebuild it
         names = set()
         for s in stubs:
-            m = re.match(r"_ZN3qap(\d+)__device_stub__(\w+)", s)
-            if not m:
-                continue
-            k = int(m.group(1)) - len("__device_stub__")
-            names.add(f"_ZN3qap{k}" + s[m.end(1) + len("__device_stub__"):])
+            m = re.match(r"(_ZN(?:\d+\w+?)*?)(\d+)__device_stub__", s)
+            assert m, f"unrecognised stub name {s}"
+            k = int(m.group(2)) - len("__device_stub__")
+            names.add(m.group(1) + str(k) + s[m.end():])
+        internal = sorted(n for n in names if "_GLOBAL__N_" in n)
+        assert not internal, ("kernels with internal linkage", internal[:3])
         assert names, f"no kernel stubs found in {obj}"
         missing = sorted(n for n in names if n not in dev)
         assert not missing, (os.path.basename(src), missing[:3])

@@ -93,3 +93,53 @@ def test_lap_device_pointers():
            "assign": [a[vo[b]: vo[b] + sizes[b]] for b in range(len(sizes))],
            "residual": [c[mo[b]: mo[b] + sizes[b] ** 2].reshape(sizes[b], sizes[b]) for b in range(len(sizes))]}
     _check(mats, out)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "fp32n"])
+def test_lap_device_buckets_match_host_bitwise(dtype):
+    """The device-pointer path sorts problems by size on the device; each
+    problem must come out bit for bit as from the host path (same segment
+    width per size), and sizes outside [0, 64] must come out unsolved (NaN)."""
+    torch = pytest.importorskip("torch")
+    from paper_1510_02065_amd import _binding as B
+    rng = np.random.default_rng(11)
+    sizes = rng.integers(0, 65, size=257).astype(np.int32)
+    sizes[:6] = [0, 1, 8, 9, 64, 33]
+    npdt = np.float64 if dtype == "fp64" else np.float32
+    tdt = torch.float64 if dtype == "fp64" else torch.float32
+    code = {"fp64": B.QAP_FP64, "fp32": B.QAP_FP32_CERTIFIED, "fp32n": B.QAP_FP32_NEAREST}[dtype]
+    mats = [qapgen.random_matrix(int(n), i, KINDS[i % 4]).astype(npdt) for i, n in enumerate(sizes)]
+    mo = np.zeros(len(sizes), np.int64)
+    vo = np.zeros(len(sizes), np.int64)
+    mo[1:] = np.cumsum(sizes.astype(np.int64) ** 2)[:-1]
+    vo[1:] = np.cumsum(sizes.astype(np.int64))[:-1]
+    cost_h = np.concatenate([m.ravel() for m in mats]).astype(npdt)
+    nv = int(sizes.sum())
+    val_h = np.empty(len(sizes))
+    dual_h = np.empty(4 * nv, npdt)
+    asg_h = np.empty(nv, np.int32)
+    st = B.lib().qap_lap_solve(len(sizes), sizes.ctypes.data, mo.ctypes.data, vo.ctypes.data, cost_h.ctypes.data,
+                               code, val_h.ctypes.data, dual_h.ctypes.data, asg_h.ctypes.data, B.QAP_LAP_RESIDUAL,
+                               None)
+    assert st == 0
+    dev = torch.device("cuda:0")
+    bad = np.array([65, -3, 70], np.int32)          # never solved: value NaN, nothing written
+    nd = torch.tensor(np.concatenate([sizes, bad]), device=dev)
+    mod = torch.tensor(np.concatenate([mo, np.zeros(3, np.int64)]), device=dev)
+    vod = torch.tensor(np.concatenate([vo, np.zeros(3, np.int64)]), device=dev)
+    cost = torch.tensor(np.concatenate([m.ravel() for m in mats]).astype(npdt), dtype=tdt, device=dev)
+    value = torch.empty(len(sizes) + 3, dtype=torch.float64, device=dev)
+    duals = torch.empty(4 * nv, dtype=tdt, device=dev)
+    assign = torch.empty(nv, dtype=torch.int32, device=dev)
+    stream = torch.cuda.Stream()
+    st = B.lib().qap_lap_solve(int(nd.numel()), nd.data_ptr(), mod.data_ptr(), vod.data_ptr(), cost.data_ptr(),
+                               code, value.data_ptr(), duals.data_ptr(), assign.data_ptr(),
+                               B.QAP_LAP_DEVICE | B.QAP_LAP_RESIDUAL, stream.cuda_stream)
+    assert st == 0
+    stream.synchronize()
+    v = value.cpu().numpy()
+    np.testing.assert_array_equal(v[: len(sizes)], val_h)
+    assert np.isnan(v[len(sizes):]).all()
+    np.testing.assert_array_equal(cost.cpu().numpy(), cost_h)
+    np.testing.assert_array_equal(duals.cpu().numpy(), dual_h)
+    np.testing.assert_array_equal(assign.cpu().numpy(), asg_h)
