@@ -305,6 +305,24 @@ qap_status qap_lap_solve(int batch, const int32_t* n, const int64_t* mat_off,
                          double* value, void* duals, int32_t* assign,
                          int flags, void* stream);
 
+/* qap_lap_solve with device pointers, allocating nothing: for callers that
+ * cannot call hipMalloc or the stream-ordered allocator (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments and results as qap_lap_solve with QAP_LAP_DEVICE (every pointer
+ * is device memory of the calling thread's current device; asynchronous on
+ * `stream`).  The size bucketing uses a static device array of the library
+ * (16 MiB, one per device, held until the process ends) instead of a
+ * workspace.  Errors: QAP_EINVAL when flags lack QAP_LAP_DEVICE or when
+ * batch > QAP_LAP_NOALLOC_MAX_BATCH; QAP_EDEVICE for HIP errors.  Every call
+ * on a device shares that device's array (each call clears what it needs on
+ * its stream first): calls that overlap on one device, on different streams
+ * or threads without ordering between them, race and give wrong results. */
+#define QAP_LAP_NOALLOC_MAX_BATCH 1048576
+qap_status qap_lap_solve_noalloc(int batch, const int32_t* n, const int64_t* mat_off,
+                                 const int64_t* vec_off, void* cost, int dtype,
+                                 double* value, void* duals, int32_t* assign,
+                                 int flags, void* stream);
+
 /* ---- stop rule, state I/O, snapshots ---------------------------------------- */
 
 /* Stop rule of Algorithm 1 (the loop runs while LB' / UB >= K and LB < UB):

@@ -64,6 +64,8 @@ SIGNATURES = {
     "qap_rlt2_destroy": (None, [_vp]),
     "qap_lap_solve": (ctypes.c_int, [ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp,
                                      ctypes.c_int, _vp]),
+    "qap_lap_solve_noalloc": (ctypes.c_int, [ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp,
+                                             ctypes.c_int, _vp]),
     "qap_last_error": (ctypes.c_char_p, []),
     "qap_rlt2_batch_create": (ctypes.c_int, [ctypes.c_int, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(Opts),
                                              ctypes.POINTER(_vp)]),

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -55,9 +56,42 @@ __global__ __launch_bounds__(256) void k_bucket(int batch, const int32_t* __rest
     lists[c * cap + pos] = (int32_t)b;
 }
 
+// Largest batch of qap_lap_solve_noalloc: its bucketing workspace is the
+// static array below, 16 MiB per device.
+constexpr long long kNoAllocMaxBatch = QAP_LAP_NOALLOC_MAX_BATCH;
+
 }  // namespace qap
 
+// Bucketing workspace of qap_lap_solve_noalloc, one copy on every device the
+// library runs on, held until the process ends.  In host code this name is a
+// host-side stand-in, not a device address: kernels and copies get the
+// device address from hipGetSymbolAddress (scratch_address below).
+static __device__ __align__(256) int32_t scratch[qap::kBucketHeader + 4 * qap::kNoAllocMaxBatch];
+
 namespace {
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+hipError_t scratch_address(int32_t** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = p;
+    }
+    *out = static_cast<int32_t*>(g_scratch_addr[dev]);
+    return hipSuccess;
+}
 
 // The device-pointer solve, given a workspace of bucket_bytes(batch) bytes:
 // clear the counters, bucket, then one launch per class with its grid sized
@@ -198,6 +232,29 @@ qap_status qap_lap_solve(int batch, const int32_t* n, const int64_t* mat_off, co
     CK2(hipStreamSynchronize(st));
 #undef CK2
     cleanup();
+    return QAP_OK;
+}
+
+qap_status qap_lap_solve_noalloc(int batch, const int32_t* n, const int64_t* mat_off, const int64_t* vec_off,
+                                 void* cost, int dtype, double* value, void* duals, int32_t* assign, int flags,
+                                 void* stream)
+{
+    qap::last_error().clear();
+    qap_status cs = check_common(batch, n, mat_off, vec_off, cost, dtype, value, duals, assign);
+    if (cs != QAP_OK || batch == 0) return cs;
+    if (!(flags & QAP_LAP_DEVICE))
+        return fail(QAP_EINVAL, "qap_lap_solve_noalloc takes device pointers only (flags must hold QAP_LAP_DEVICE)");
+    if (batch > qap::kNoAllocMaxBatch)
+        return fail(QAP_EINVAL, "batch exceeds QAP_LAP_NOALLOC_MAX_BATCH (" +
+                                    std::to_string(qap::kNoAllocMaxBatch) + ") problems");
+    int32_t* ws = nullptr;
+    hipError_t e = scratch_address(&ws);
+    if (e != hipSuccess) return fail(QAP_EDEVICE, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+    e = solve_device(batch, n, mat_off, vec_off, cost, dtype, value, duals, assign,
+                     (flags & QAP_LAP_RESIDUAL) ? 1 : 0,
+                     (flags & QAP_LAP_AUCTION) ? QAP_LAP_SOLVER_AUCTION : QAP_LAP_SOLVER_CANONICAL,
+                     static_cast<hipStream_t>(stream), ws);
+    if (e != hipSuccess) return fail(QAP_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     return QAP_OK;
 }
 
