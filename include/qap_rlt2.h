@@ -126,6 +126,12 @@ typedef struct {
                          is steps 1, 5, 6, 7 and 8), the dual of the strong
                          branching of Section 6                              */
     int lap_solver;    /* qap_lap_solver of the concentrations (default 0)    */
+    int overlap;       /* 1 (default): in a batch of instances of several
+                         sizes, qap_rlt2_ascend runs the sweep of each size
+                         and then its D->C concentration on a second stream,
+                         beside the next size's sweep (both streams at the
+                         default priority; the same results bit for bit);
+                         0: one step after the other                         */
 } qap_rlt2_opts;
 
 typedef struct qap_rlt2 qap_rlt2;

@@ -32,7 +32,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("trace_level", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("tune_cache", ctypes.c_char_p), ("complementary", ctypes.c_int), ("K", ctypes.c_double),
-                ("UB", ctypes.c_double), ("level", ctypes.c_int), ("lap_solver", ctypes.c_int)]
+                ("UB", ctypes.c_double), ("level", ctypes.c_int), ("lap_solver", ctypes.c_int),
+                ("overlap", ctypes.c_int)]
 
 
 class BnbParams(ctypes.Structure):
@@ -140,7 +141,8 @@ def _dptr(a):
 
 
 def _opts(precision, trace_level, use_graph, device, stream, autotune=True, tune_cache=None,
-          complementary=True, K=0.0, UB=0.0, level=2, lap_solver="canonical"):
+          complementary=True, K=0.0, UB=0.0, level=2, lap_solver="canonical",
+          overlap=True):
     opts = Opts()
     _check(lib().qap_rlt2_default_opts(ctypes.byref(opts)), "qap_rlt2_default_opts")
     opts.precision = PRECISIONS[precision]
@@ -148,6 +150,7 @@ def _opts(precision, trace_level, use_graph, device, stream, autotune=True, tune
     opts.UB = float(UB)
     opts.level = int(level)
     opts.lap_solver = SOLVERS[lap_solver]
+    opts.overlap = 1 if overlap else 0
     opts.device = device
     opts.stream = stream
     opts.trace_level = trace_level
@@ -165,7 +168,8 @@ class Rlt2:
 
     def __init__(self, F, D, B0=None, constant=0.0, precision="fp64", trace_level=1,
                  use_graph=True, device=-1, stream=None, autotune=True, tune_cache=None,
-                 complementary=True, K=0.0, UB=0.0, level=2, lap_solver="canonical"):
+                 complementary=True, K=0.0, UB=0.0, level=2, lap_solver="canonical",
+          overlap=True):
         L = lib()
         F = _f64(F)
         D = _f64(D)
@@ -174,7 +178,7 @@ class Rlt2:
             raise ValueError("F and D must be square and of the same size")
         B0 = None if B0 is None else _f64(B0)
         opts = _opts(precision, trace_level, use_graph, device, stream, autotune, tune_cache, complementary,
-                     K, UB, level, lap_solver)
+                     K, UB, level, lap_solver, overlap)
         h = _vp()
         _check(L.qap_rlt2_create_ex(N, _dptr(F), _dptr(D), _dptr(B0), float(constant),
                                     ctypes.byref(opts), ctypes.byref(h)), "qap_rlt2_create_ex")
@@ -186,7 +190,8 @@ class Rlt2:
     @classmethod
     def batch(cls, Fs, Ds, B0s=None, constants=None, precision="fp64", trace_level=1,
               use_graph=True, device=-1, stream=None, autotune=True, tune_cache=None,
-              complementary=True, K=0.0, UB=0.0, level=2, lap_solver="canonical"):
+              complementary=True, K=0.0, UB=0.0, level=2, lap_solver="canonical",
+          overlap=True):
         """Many instances (e.g. branch-and-bound nodes) in one handle."""
         count = len(Fs)
         Fs = [_f64(F) for F in Fs]
@@ -198,7 +203,7 @@ class Rlt2:
         dp = (ctypes.c_void_p * count)(*[D.ctypes.data for D in Ds])
         bp = (ctypes.c_void_p * count)(*[None if B is None else B.ctypes.data for B in B0s])
         opts = _opts(precision, trace_level, use_graph, device, stream, autotune, tune_cache, complementary,
-                     K, UB, level, lap_solver)
+                     K, UB, level, lap_solver, overlap)
         h = _vp()
         _check(lib().qap_rlt2_batch_create(count, Ns.ctypes.data, ctypes.cast(fp, _vp), ctypes.cast(dp, _vp),
                                            ctypes.cast(bp, _vp), consts.ctypes.data, ctypes.byref(opts),

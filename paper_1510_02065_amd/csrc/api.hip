@@ -96,6 +96,12 @@ hipError_t enqueue_step_any(qap_rlt2* h, int step) { return QAP_OPS(h->precision
 
 hipError_t enqueue_iteration(qap_rlt2* h)
 {
+    if (h->overlap) {
+        hipError_t e = QAP_OPS(h->precision, enqueue_sweep_concentrate_overlapped(h));
+        for (int s : {5, 6, 7})
+            if (e == hipSuccess) e = enqueue_step_any(h, s);
+        return e;
+    }
     for (int s : {3, 4, 5, 6, 7}) {
         hipError_t e = enqueue_step_any(h, s);
         if (e != hipSuccess) return e;
@@ -173,6 +179,15 @@ void release(qap_rlt2* h)
         if (c.d_ids) (void)hipFree(c.d_ids);
         if (c.d_pre) (void)hipFree(c.d_pre);
     }
+    for (auto& c : h->famD_size) {
+        if (c.d_ids) (void)hipFree(c.d_ids);
+        if (c.d_pre) (void)hipFree(c.d_pre);
+    }
+    for (hipEvent_t ev : h->ev_size)
+        if (ev) (void)hipEventDestroy(ev);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->stream2) (void)hipStreamDestroy(h->stream2);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
 
@@ -373,6 +388,29 @@ qap_status make_handle(int count, const int32_t* Ns, const qap_rlt2_opts& o, qap
             if (c.seg_run == 0) return bail(fail(QAP_EINVAL, "problem size needs more LDS than a workgroup has"));
         }
 
+    // The overlapped schedule: the D family split by instance size, in the
+    // sweep classes' order, a second stream and the events between them.
+    if (o.overlap && h->level == 2 && h->dmode == qap::kHalfStore && h->sweep_cls.size() > 1) {
+        for (const qap::SweepClass& sc : h->sweep_cls) {
+            qap::ClassHost c;
+            c.nmax = sc.N - 2;
+            c.seg = qap::seg_for(c.nmax);
+            for (int k : sc.ids) {
+                const long long N = h->inst[k].N;
+                c.ids.push_back(k);
+                c.pre.push_back(c.total);
+                c.total += N * N * (N - 1) * (N - 1) / 2;
+            }
+            h->famD_size.push_back(std::move(c));
+        }
+        CK(hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking));
+        h->ev_size.assign(h->sweep_cls.size(), nullptr);
+        for (hipEvent_t& ev : h->ev_size) CK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        CK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        CK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+        h->overlap = true;
+    }
+
     const size_t bytesD = (size_t)h->totalD * h->elem;
     size_t freeb = 0, totalb = 0;
     CK(hipMemGetInfo(&freeb, &totalb));
@@ -413,6 +451,10 @@ qap_status make_handle(int count, const int32_t* Ns, const qap_rlt2_opts& o, qap
             CK(upload(&c.d_ids, c.ids, h->stream));
             CK(upload(&c.d_pre, c.pre, h->stream));
         }
+    for (auto& c : h->famD_size) {
+        CK(upload(&c.d_ids, c.ids, h->stream));
+        CK(upload(&c.d_pre, c.pre, h->stream));
+    }
     if (h->autotune) load_tune_cache(h);
     const std::vector<int> ones(count, 1);
     const double stop[2] = {h->stopK, h->stopUB};
@@ -541,6 +583,7 @@ qap_status qap_rlt2_default_opts(qap_rlt2_opts* o)
     o->UB = 0.0;
     o->level = 2;
     o->lap_solver = QAP_LAP_SOLVER_CANONICAL;
+    o->overlap = 1;
     return QAP_OK;
 }
 
@@ -1148,6 +1191,7 @@ qap_status qap_rlt2_children(qap_rlt2* h, int k, int count, const int32_t* fac, 
     o.UB = h->stopUB;
     o.level = level;
     o.lap_solver = h->lap_solver;
+    o.overlap = h->overlap ? 1 : 0;
     std::vector<int32_t> Ns(count, N - 1);
     qap_rlt2* c = nullptr;
     if ((st = make_handle(count, Ns.data(), o, &c)) != QAP_OK) return st;

@@ -131,6 +131,15 @@ struct qap_rlt2 {
     qap::ClassHost fam[3][4];   // [D, C, B][segment class]
     std::vector<qap::SweepClass> sweep_cls;   // empty: one sweep launch over every instance
     int sweep_nt = 0;                         // that launch: threads of a per-triple workgroup (0: persistent)
+    // Overlapped steps 1-4 of a batch of mixed sizes (qap_rlt2_ascend): the
+    // sweep of each size runs on `stream`, and the D->C concentration of that
+    // size on `stream2` as soon as its sweep is done, so one size's
+    // assignment problems run beside the next size's sweep.
+    bool overlap = false;
+    hipStream_t stream2 = nullptr;
+    std::vector<qap::ClassHost> famD_size;    // D family of each sweep class's instances (same order)
+    std::vector<hipEvent_t> ev_size;          // one per sweep class: its sweep is done
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<int> tri;                     // facility triples of every instance
     qap::Inst* dInst = nullptr;
     long long *dPreB = nullptr, *dPreC = nullptr, *dPreWG = nullptr;
@@ -187,6 +196,9 @@ struct Ops {
     // Children of parent instance pk of handle ph (fixings fix[2c], fix[2c+1]
     // in device memory) into handle ch, whose instances are those children.
     static hipError_t inherit(qap_rlt2* ph, int pk, qap_rlt2* ch, const int* dfix);
+    // Steps 1-4 with each size's concentration overlapped with the next
+    // size's sweep (h->overlap).
+    static hipError_t enqueue_sweep_concentrate_overlapped(qap_rlt2* h);
 };
 
 extern template struct Ops<kPrecF64>;

@@ -69,6 +69,19 @@ __device__ __forceinline__ void stage_block(T* __restrict__ M, const T* __restri
     }
 }
 
+// XCD-aware order of the assignment workgroups.  The hardware hands
+// workgroup b to XCD b mod 8, and each XCD has its own L2; consecutive
+// problems' block rows are adjacent in memory (they share the 128-byte lines
+// at their ends), so each XCD takes one contiguous range of the workgroups'
+// problems: workgroup b runs position xcd_major(b) of the problem order,
+// ranges of q or q + 1 positions (q = grid / 8, the first grid % 8 XCDs
+// taking one more).  A bijection of [0, grid).
+__device__ __forceinline__ long long xcd_major(long long b, long long grid)
+{
+    const long long q = grid >> 3, r = grid & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // D -> C (FAM kFamD: blocks D_beta of size N-2, parent c_beta) or C -> B
 // (kFamC: blocks C_ij of size N-1, parent b_ij), K columns per lane, 64/SEG
 // problems per wave, one wave per workgroup.  parent += S, the block is
@@ -87,7 +100,7 @@ __global__ __launch_bounds__(64) void k_lap_family_s(StoreT<PM>* __restrict__ D,
     constexpr int LPW = 64 / SEG;
     const int seg = threadIdx.x / SEG;
     const int lane = threadIdx.x & (SEG - 1);
-    const long long x = (long long)blockIdx.x * LPW + seg;
+    const long long x = xcd_major(blockIdx.x, gridDim.x) * LPW + seg;
     int kk = 0;
     if (x < fc.total) kk = find_seg(fc.pre, fc.Kc, x);
     const bool active = x < fc.total && act[fc.cls[kk]];

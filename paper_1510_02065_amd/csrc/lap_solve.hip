@@ -42,18 +42,30 @@ __global__ __launch_bounds__(64) void k_bucket_clear(int32_t* __restrict__ count
     if (threadIdx.x < 4) counts[threadIdx.x] = 0;
 }
 
-// One thread per problem: append b to the list of its size class.  The order
-// within a list is not fixed; each problem's result depends only on its own
-// matrix and the segment width, so it does not matter.
+// One thread per problem: append b to the list of its size class.  Each wave
+// reserves the places of its problems of a class with one atomic on that
+// class's counter (a ballot gives the count and each lane's rank), so the
+// counters see one request per wave and class instead of one per problem.
+// The order within a list is not fixed; each problem's result depends only
+// on its own matrix and the segment width, so it does not matter.
 __global__ __launch_bounds__(256) void k_bucket(int batch, const int32_t* __restrict__ n,
                                                 int32_t* __restrict__ counts, int32_t* __restrict__ lists,
                                                 long long cap)
 {
     const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch) return;
-    const int c = size_class(n[b]);
-    const int pos = atomicAdd(&counts[c], 1);
-    lists[c * cap + pos] = (int32_t)b;
+    const bool in = b < batch;
+    const int c = in ? size_class(n[b]) : -1;
+    const unsigned lane = threadIdx.x & 63u;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int k = 0; k < 4; ++k) {
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(c == k);
+        if (m == 0ull) continue;
+        const int leader = __builtin_ctzll(m);
+        int base = 0;
+        if ((int)lane == leader) base = atomicAdd(&counts[k], __builtin_popcountll(m));
+        base = __builtin_amdgcn_readlane(base, leader);
+        if (c == k) lists[k * cap + base + __builtin_popcountll(m & below)] = (int32_t)b;
+    }
 }
 
 // Largest batch of qap_lap_solve_noalloc: its bucketing workspace is the

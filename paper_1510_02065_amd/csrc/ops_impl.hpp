@@ -258,6 +258,40 @@ hipError_t Ops<PM>::enqueue_step(qap_rlt2* h, int step)
 }
 
 template <int PM>
+hipError_t Ops<PM>::enqueue_sweep_concentrate_overlapped(qap_rlt2* h)
+{
+    using T = StoreT<PM>;
+    hipStream_t A = h->stream, Bs = h->stream2;
+    hipLaunchKernelGGL((k_spread_prep<PM>), dim3(grid_for(h->totalC, 256)), dim3(256), 0, A, static_cast<T*>(h->dC),
+                       static_cast<T*>(h->dB), static_cast<T*>(h->dCC), h->dInst, h->dPreC, h->K, h->totalC,
+                       h->dAct);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(h->ev_fork, A)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(Bs, h->ev_fork, 0)) != hipSuccess) return e;
+    for (size_t i = 0; i < h->sweep_cls.size() && e == hipSuccess; ++i) {
+        const SweepClass& c = h->sweep_cls[i];
+        e = launch_triple<PM>(h, c.d_pre, c.d_ids, (int)c.ids.size(), c.ntri, c.N, c.nt);
+        if (e == hipSuccess) e = hipEventRecord(h->ev_size[i], A);
+        if (e == hipSuccess) e = hipStreamWaitEvent(Bs, h->ev_size[i], 0);
+        if (e != hipSuccess) break;
+        // The concentration of this size, on the second stream, with the
+        // configuration tuned for its segment-size class.
+        const ClassHost& d = h->famD_size[i];
+        const ClassHost& bucket = h->fam[kFamD][d.seg == 8 ? 0 : d.seg == 16 ? 1 : d.seg == 32 ? 2 : 3];
+        double* vals = h->trace_level >= 2 ? h->dValD : nullptr;
+        h->stream = Bs;
+        e = h->lap_solver == QAP_LAP_SOLVER_AUCTION
+                ? launch_family_auction<PM>(h, kFamD, d, vals, h->dmode)
+                : launch_family_class<PM>(h, kFamD, d, d.dev(), bucket.seg_run, bucket.k_run, vals, h->dmode);
+        h->stream = A;
+    }
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(h->ev_join, Bs)) != hipSuccess) return e;
+    return hipStreamWaitEvent(A, h->ev_join, 0);
+}
+
+template <int PM>
 hipError_t Ops<PM>::certify(qap_rlt2* h)
 {
     using T = StoreT<PM>;

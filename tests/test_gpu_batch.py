@@ -125,3 +125,27 @@ def test_c3_nodes_fp64_fp32_and_oracle_sample():
         assert cert[k10[0]] <= opt
     g.close()
     f.close()
+
+
+@pytest.mark.parametrize("precision,use_graph", [("fp64", True), ("fp32", True), ("fp64", False)])
+def test_overlapped_schedule_equals_sequential_bitwise(precision, use_graph):
+    # Mixed sizes: with overlap each size's D->C concentration runs on a
+    # second stream beside the next size's sweep; the state, the traces and
+    # every per-LAP value must be those of the one-step-after-another run.
+    _, _, nodes = _nodes(20, 24, 11, 2, 9)
+    print(f"overlap vs sequential, {precision}, graph={use_graph}, N' =",
+          sorted({n[0].shape[0] for n in nodes}), flush=True)
+    args = ([n[0] for n in nodes], [n[1] for n in nodes], [n[2] for n in nodes], [n[3] for n in nodes])
+    a = Rlt2.batch(*args, precision=precision, trace_level=2, use_graph=use_graph, overlap=True)
+    b = Rlt2.batch(*args, precision=precision, trace_level=2, use_graph=use_graph, overlap=False)
+    a.ascend(5)
+    b.ascend(5)
+    np.testing.assert_array_equal(a.bounds(), b.bounds())
+    for k in range(len(nodes)):
+        np.testing.assert_array_equal(a.trace_k(k)[0], b.trace_k(k)[0])
+        for x, y in zip(a.lap_values_k(k), b.lap_values_k(k)):
+            np.testing.assert_array_equal(x, y)
+        for x, y in zip(a.read_state_k(k)[1:], b.read_state_k(k)[1:]):
+            np.testing.assert_array_equal(x, y)
+    a.close()
+    b.close()
