@@ -141,6 +141,8 @@ __global__ __launch_bounds__(64) void k_lap_family_s(StoreT<PM>* __restrict__ D,
         S = lap_auction_flat<T, SEG, DOWN>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
     else if constexpr (K == 1)
         S = lap_concentrate_flat<T, SEG, DOWN>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
+    else if constexpr (SEG >= 16)
+        S = lap_concentrate_flatk<T, SEG, K, DOWN>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
     else
         S = lap_concentrate_slots<T, SEG, K, DOWN>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
     if (active && lane == 0) {
@@ -192,6 +194,8 @@ __global__ __launch_bounds__(64) void k_lap_B_s(StoreT<PM>* __restrict__ B, cons
         S = lap_auction_flat<T, SEG, DOWN>(sc, n, active ? blk : nullptr, n, nullptr, sg);
     else if constexpr (K == 1)
         S = lap_concentrate_flat<T, SEG, DOWN>(sc, n, active ? blk : nullptr, n, nullptr, sg);
+    else if constexpr (SEG >= 16)
+        S = lap_concentrate_flatk<T, SEG, K, DOWN>(sc, n, active ? blk : nullptr, n, nullptr, sg);
     else
         S = lap_concentrate_slots<T, SEG, K, DOWN>(sc, n, active ? blk : nullptr, n, nullptr, sg);
     if (active && lane == 0) {

@@ -963,4 +963,249 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
     }
 }
 
+// canonical_split for K columns per lane (n <= SEG * K, SEG >= 16): the two
+// half segments of SEG/2 lanes run the column and the row pass side by side,
+// each lane holding the 2K nodes h, h + SEG/2, ..., h + (2K-1) SEG/2.  Same
+// decisions and operations as canonical_split (and lap_canonical_finish):
+// the lowest node at the minimum, relaxations (M - per-step dual) - per-node
+// dual.  poff[s] is the offset r*n of the row matched to column c_s (-1 when
+// none); on return vc, ur and sg hold, for each of the lane's columns c_s
+// (rows c_s), the column-canonical dual, the row-canonical dual and the
+// row's column.
+template <typename T, int SEG, int K>
+__device__ __forceinline__ void canonical_split_k(const SlotScratch<T, SEG, K>& sc, int n, const T (&v)[K],
+                                                  const int (&poff)[K], T (&vc)[K], T (&ur)[K], int (&sg)[K])
+{
+    static_assert(SEG >= 16, "two half segments of at least 8 lanes");
+    constexpr int H = SEG / 2;
+    constexpr int NQ = 2 * K;
+    constexpr int NONE = 1 << 20;
+    using HS = SegS<H>;
+    const T* __restrict__ M = sc.M;
+    const int l = threadIdx.x & (SEG - 1);
+    const T INF = inf_of<T>();
+    for (int s = 0; s < K; ++s) {
+        const int c = s * SEG + l;
+        if (c >= n) continue;
+        const int prow = poff[s] >= 0 ? poff[s] / n : -1;
+        if (prow >= 0 && prow < n) sc.aux[prow] = c;
+        sc.vb[c] = (double)v[s];
+    }
+    wave_sync();
+    const bool rowpass = l >= H;
+    const int h = l & (H - 1);
+    int t[NQ], base[NQ];
+    T lab[NQ], w[NQ];
+    bool fx[NQ];
+    for (int q = 0; q < NQ; ++q) {
+        t[q] = h + q * H;
+        const bool okn = t[q] < n;
+        const int tc = okn ? t[q] : 0;
+        if (rowpass) {
+            int sgt = sc.aux[tc];
+            sgt = (sgt >= 0 && sgt < n) ? sgt : 0;
+            w[q] = (T)sc.u[sgt];
+        } else {
+            w[q] = (T)sc.vb[tc];
+        }
+        lab[q] = okn ? -w[q] : (T)0;
+        fx[q] = !okn;
+        base[q] = rowpass ? tc * n : tc;
+    }
+    for (int step = 0; step < n; ++step) {
+        T m = fx[0] ? INF : lab[0];
+        for (int q = 1; q < NQ; ++q) m = tmin(m, fx[q] ? INF : lab[q]);
+        const T dmin = HS::min(m);
+        int cand = NONE;
+        for (int q = NQ - 1; q >= 0; --q)
+            if (!fx[q] && lab[q] == dmin) cand = t[q];
+        const int f = HS::imin(cand);
+        const int fc = f < n ? f : 0;
+        const int key = rowpass ? sc.aux[fc] : (int)sc.p[fc];
+        const T s1 = rowpass ? (T)sc.vb[key] : (T)sc.u[fc];
+        for (int q = 0; q < NQ; ++q) {
+            fx[q] = fx[q] || (t[q] == f);
+            const T nd = dmin + ((M[base[q] + key] - s1) - w[q]);
+            if (!fx[q] && nd < lab[q]) lab[q] = nd;
+        }
+    }
+    wave_sync();
+    for (int q = 0; q < NQ; ++q) {
+        if (t[q] < n) {
+            if (rowpass)
+                sc.u[t[q]] = (double)(w[q] + lab[q]);
+            else
+                sc.vb[t[q]] = (double)(w[q] + lab[q]);
+        }
+    }
+    wave_sync();
+    for (int s = 0; s < K; ++s) {
+        const int c = s * SEG + l;
+        const int cc = c < n ? c : 0;
+        vc[s] = (T)sc.vb[cc];
+        ur[s] = (T)sc.u[cc];
+        sg[s] = sc.aux[cc];
+    }
+    wave_sync();
+}
+
+// lap_concentrate_flat for K columns per lane (n <= SEG * K, SEG >= 16):
+// the free rows of all the wave's problems inserted in one loop, each lane
+// holding columns c_s = s*SEG + lane.  Per Dijkstra step every lane scans its
+// K columns, the segment minimum runs over the lanes' smallest, and the
+// lowest column at the minimum is the lowest lane of the lowest slot whose
+// ballot is not empty.  Same decisions and arithmetic as
+// lap_concentrate_slots.
+template <typename T, int SEG, int K, bool DOWN>
+__device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG, K>& sc, int n,
+                                                        T* __restrict__ R, long long ldr, T* __restrict__ duals,
+                                                        int32_t* __restrict__ assign)
+{
+    static_assert(SEG >= 16 && K >= 2, "several columns per lane, half segments of at least 8 lanes");
+    using S = SegS<SEG>;
+    using Bits = SegBits<SEG>;
+    const T* __restrict__ M = sc.M;
+    const int l = S::lane();
+    const T INF = inf_of<T>();
+    int c[K];
+    bool ok[K];
+    for (int s = 0; s < K; ++s) {
+        c[s] = s * SEG + l;
+        ok[s] = c[s] < n;
+    }
+
+    // ---- two-sided reduction and greedy start -------------------------------
+    T v[K];
+    int poff[K];   // offset r * n of the row matched to each column, -1 when free
+    T ucol[K];     // dual of that row
+    unsigned long long freem;
+    {
+        int rw[K];
+        const unsigned long long taken = lap_reduce_start<T, SEG, K>(sc, n, c, ok, v, rw);
+        for (int s = 0; s < K; ++s) {
+            poff[s] = rw[s] >= 0 ? rw[s] * n : -1;
+            ucol[s] = rw[s] >= 0 ? (T)sc.vb[rw[s]] : (T)0;
+        }
+        freem = ~taken & (n >= 64 ? ~0ull : ((1ull << n) - 1ull));
+    }
+    wave_sync();
+    for (int s = 0; s < K; ++s) {
+        if (!ok[s]) continue;
+        sc.p[c[s]] = poff[s];
+        sc.u[c[s]] = (double)ucol[s];
+    }
+    wave_sync();
+
+    // ---- Hungarian method, all problems of the wave together -----------------
+    int row = freem ? __builtin_ctzll(freem) : -1;
+    freem &= freem - 1;
+    T dist[K];
+    int way[K];
+    bool used[K];
+    for (int s = 0; s < K; ++s) {
+        dist[s] = INF;
+        way[s] = -1;
+        used[s] = false;
+    }
+    int i0n = row >= 0 ? row * n : 0;
+    T urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;
+    T ui0 = urow0;
+    T d0 = 0;
+    int j0 = -1;
+    while (ballot64(row >= 0) != 0) {
+        const bool active = row >= 0;
+        bool live[K];
+        T lm[K];
+        for (int s = 0; s < K; ++s) {
+            live[s] = active && ok[s] && !used[s];
+            const T cur = d0 + ((M[i0n + (ok[s] ? c[s] : 0)] - ui0) - v[s]);
+            if (live[s] && cur < dist[s]) {
+                dist[s] = cur;
+                way[s] = j0;
+            }
+            lm[s] = live[s] ? dist[s] : INF;
+        }
+        T lmin = lm[0];
+        for (int s = 1; s < K; ++s) lmin = tmin(lmin, lm[s]);
+        const T dmin = S::min(lmin);
+        int j1 = -1;
+        for (int s = 0; s < K; ++s) {
+            const unsigned long long bs = Bits::get(live[s] && lm[s] == dmin);
+            if (j1 < 0 && bs != 0ull) j1 = s * SEG + Bits::first(bs);
+        }
+        const int jc = j1 >= 0 ? j1 : 0;
+        const int pj = sc.p[jc];
+        const T uj = (T)sc.u[jc];
+        const bool aug = active && (j1 < 0 || pj < 0);
+        for (int s = 0; s < K; ++s) used[s] = used[s] || (c[s] == j1);
+        j0 = j1;
+        i0n = pj >= 0 ? pj : 0;
+        ui0 = uj;
+        d0 = dmin;
+        if (ballot64(aug) != 0) {
+            if (aug) {
+                for (int s = 0; s < K; ++s) {
+                    if (used[s]) {
+                        const T sh = dmin - dist[s];
+                        v[s] -= sh;
+                        ucol[s] += sh;
+                    }
+                    if (ok[s]) {
+                        sc.way[c[s]] = way[s];
+                        sc.u[c[s]] = (double)ucol[s];
+                    }
+                }
+            }
+            wave_sync();
+            int newp[K];
+            T newu[K];
+            for (int s = 0; s < K; ++s) {
+                newp[s] = poff[s];
+                newu[s] = ucol[s];
+            }
+            if (aug) {
+                bool onpath[K];
+                for (int s = 0; s < K; ++s) onpath[s] = false;
+                for (int j = j1, hop = 0; j >= 0 && hop <= n; ++hop) {
+                    for (int s = 0; s < K; ++s) onpath[s] = onpath[s] || (c[s] == j);
+                    j = sc.way[j];
+                }
+                for (int s = 0; s < K; ++s) {
+                    if (!onpath[s]) continue;
+                    const int wc = way[s] >= 0 ? way[s] : 0;
+                    newp[s] = way[s] >= 0 ? (int)sc.p[wc] : row * n;
+                    newu[s] = way[s] >= 0 ? (T)sc.u[wc] : urow0 + dmin;
+                }
+            }
+            wave_sync();
+            if (aug) {
+                for (int s = 0; s < K; ++s) {
+                    poff[s] = newp[s];
+                    ucol[s] = newu[s];
+                    if (ok[s]) {
+                        sc.p[c[s]] = poff[s];
+                        sc.u[c[s]] = (double)ucol[s];
+                    }
+                    dist[s] = INF;
+                    way[s] = -1;
+                    used[s] = false;
+                }
+                row = freem ? __builtin_ctzll(freem) : -1;
+                freem &= freem - 1;
+                i0n = row >= 0 ? row * n : 0;
+                urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;
+                ui0 = urow0;
+                d0 = 0;
+                j0 = -1;
+            }
+            wave_sync();
+        }
+    }
+
+    T vc[K], ur[K];
+    int sg[K];
+    canonical_split_k<T, SEG, K>(sc, n, v, poff, vc, ur, sg);
+    return lap_complete<T, SEG, K, DOWN>(sc, n, R, ldr, duals, assign, vc, ur, sg);
+}
+
 }  // namespace qap

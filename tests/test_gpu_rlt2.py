@@ -216,3 +216,28 @@ def test_slot_configurations_agree_bitwise(tmp_path, precision):
         else:
             for x, y in zip(got, ref):
                 np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32n"])
+def test_slot_configurations_agree_bitwise_n23(tmp_path, precision):
+    # The benchmark's size: n = 23 (D family) and 24 (C family) in the
+    # 32-lane bucket, forced to one column per lane on 32 lanes, two columns
+    # per lane on 16 lanes (several problems' free rows in one loop) and three
+    # columns per lane on 8 lanes (one free row at a time).
+    F, D = qapgen.clustered(25, 0)
+    prec = {"fp64": 0, "fp32": 1, "fp32n": 2}[precision]
+    ref = None
+    for seg, k in [(32, 1), (16, 2), (8, 3), (32, 2)]:
+        cache = tmp_path / f"tune25_{seg}_{k}.txt"
+        cache.write_text(f"gfx950 prec={prec} fam=0 seg=32 nmax=23|{seg} {k}\n"
+                         f"gfx950 prec={prec} fam=1 seg=32 nmax=24|{seg} {k}\n")
+        print(f"configuration SEG={seg} K={k} {precision} N=25", flush=True)
+        h = Rlt2(F, D, precision=precision, trace_level=2, tune_cache=cache)
+        h.ascend(3)
+        got = (h.trace()[0], *h.read_state()[1:], *h.lap_values()[:2])
+        h.close()
+        if ref is None:
+            ref = got
+        else:
+            for x, y in zip(got, ref):
+                np.testing.assert_array_equal(x, y)
