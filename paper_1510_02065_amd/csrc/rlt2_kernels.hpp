@@ -35,9 +35,10 @@ __device__ __forceinline__ int drop2(int x, int a, int b) { return x - (x > a) -
 // sequential reference, and so match it bit for bit.
 //
 // FP32 nearest mode: reduced costs are stored as floats; every value written
-// into the state is computed in FP64 with the FP64 mode's operations and
-// rounded to nearest once, so the FP32 state follows the FP64 trajectory
-// without a systematic bias.
+// into the state is computed in FP64 with the FP64 mode's operations (the
+// six-way mean multiplying by 1/6 instead of dividing by 6) and rounded to
+// nearest once, so the FP32 state follows the FP64 trajectory without a
+// systematic bias.
 //
 // FP32 certified mode: reduced costs are stored as floats, and every value
 // written into the state (B, C, D, LB) is computed in FP64 and rounded
@@ -450,7 +451,14 @@ __global__ __launch_bounds__(256) void k_sweep(StoreT<PM>* __restrict__ Dd, cons
         s += m3;
         s += m4;
         s += m5;
-        mean = (T)(s / 6.0);
+        // FP64: IEEE division (the oracle's operation, bit for bit); FP32
+        // nearest: the FP64 sum times 1/6, rounded to float once (the
+        // division's correctly rounded FP64 quotient would only matter for
+        // the rare sum within one FP64 ulp of a float rounding boundary).
+        if constexpr (PM == kPrecF64)
+            mean = (T)(s / 6.0);
+        else
+            mean = (T)(s * (1.0 / 6.0));
     } else {
         mean = mean6_down(Dk[a0], CCk[b0], Dk[a1], CCk[b1], Dk[a2], CCk[b2], Dk[a3], CCk[b3], Dk[a4], CCk[b4],
                           Dk[a5], CCk[b5]);
@@ -501,7 +509,10 @@ __device__ __forceinline__ T six_way_mean(T A0, T B0, T C0, T x0, T x1, T x2, T 
         sum += m3;
         sum += m4;
         sum += m5;
-        return (T)(sum / 6.0);
+        if constexpr (PM == kPrecF64)
+            return (T)(sum / 6.0);   // the oracle's operation, bit for bit
+        else
+            return (T)(sum * (1.0 / 6.0));   // rounded to float once (see k_sweep)
     } else {
         return mean6_down(A0, x0, B0, x1, A0, x2, C0, x3, B0, x4, C0, x5);
     }

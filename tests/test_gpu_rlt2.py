@@ -241,3 +241,52 @@ def test_slot_configurations_agree_bitwise_n23(tmp_path, precision):
         else:
             for x, y in zip(got, ref):
                 np.testing.assert_array_equal(x, y)
+
+
+# ---- closed forms and symmetries on the GPU (no oracle involved) -------------------
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32n"])
+def test_closed_forms_flow_all_ones_and_zero(precision):
+    # F = J - I: every permutation costs the sum of D's off-diagonal entries,
+    # so LB_0 is the optimum and no iteration moves anything (LB' = 0).
+    # F = 0: every bound is 0.
+    N = 9
+    _, Dm = qapgen.small(N, 4)
+    F = np.ones((N, N)) - np.eye(N)
+    total = Dm.sum()
+    g = Rlt2(F, Dm, precision=precision)
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    assert g.bound()[0] == pytest.approx(total, rel=tol)
+    g.ascend(4)
+    lb, lbp = g.trace()
+    assert np.abs(lb - total).max() <= tol * total
+    assert np.abs(lbp[1:]).max() <= tol * total
+    if precision == "fp32":
+        assert (lb <= total).all()
+    g.close()
+    z = Rlt2(np.zeros((N, N)), Dm, precision=precision)
+    z.ascend(3)
+    assert (z.trace()[0] == 0.0).all()
+    z.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32n"])
+def test_relabel_and_flow_distance_swap_invariance(precision):
+    # The canonical dual is equivariant under relabelling rows and columns and
+    # transpose-symmetric, so relabelling facilities and locations, and
+    # swapping F and D (the QAP of the inverse permutation), leave the whole
+    # bound trajectory unchanged up to rounding.
+    F, Dm = qapgen.uniform(12, 5)
+    rng = np.random.default_rng(9)
+    P = rng.permutation(12)
+    Q = rng.permutation(12)
+    runs = [(F, Dm), (F[np.ix_(P, P)], Dm[np.ix_(Q, Q)]), (Dm, F)]
+    trajs = []
+    for Fx, Dx in runs:
+        g = Rlt2(Fx, Dx, precision=precision)
+        g.ascend(8)
+        trajs.append(g.trace()[0])
+        g.close()
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for t in trajs[1:]:
+        np.testing.assert_allclose(t, trajs[0], rtol=tol)
