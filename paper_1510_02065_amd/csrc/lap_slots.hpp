@@ -427,11 +427,22 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             }
             if (assign != nullptr) assign[c[s]] = sg[s];
         }
-        auto down = [](double a, double b) { return add_down(a, b); };
-        const double su = tree_sum64<SEG, K>(U, down);
-        const double sv = tree_sum64<SEG, K>(V, down);
+        // S = sum U + sum V rounded down: each sum over the 64 column slots
+        // is taken in round-to-nearest (six levels of pairwise additions, so
+        // within (1 + 2^-53)^6 - 1 < 7 * 2^-53 of the exact sum relative to
+        // the sum of magnitudes) and lowered by 2^-48 times the
+        // round-to-nearest sum of the magnitudes, which covers that error and
+        // the lowering's own rounding.
+        auto plus = [](double a, double b) { return a + b; };
+        double aU[K], aV[K];
+        for (int s = 0; s < K; ++s) {
+            aU[s] = __builtin_fabs(U[s]);
+            aV[s] = __builtin_fabs(V[s]);
+        }
+        const double su = tree_sum64<SEG, K>(U, plus), sau = tree_sum64<SEG, K>(aU, plus);
+        const double sv = tree_sum64<SEG, K>(V, plus), sav = tree_sum64<SEG, K>(aV, plus);
         wave_sync();
-        return add_down(su, sv);
+        return add_down(su - sau * 0x1p-48, sv - sav * 0x1p-48);
     }
 }
 
