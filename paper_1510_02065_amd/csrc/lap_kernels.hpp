@@ -34,8 +34,10 @@ enum DStorage : int {
 // n).  Each lane issues the loads of a whole chunk of rows before it writes
 // any of them, so a wave waits for HBM once per chunk instead of once per row:
 // the first kStageRows rows (all of them up to n = 24) in straight-line code,
-// the rest kStageTail at a time.  Rows past the end re-read row n-1 and are
-// not written.  Row offsets are 32-bit (n * ld < 2^31 for n <= 64).
+// the rest kStageTail at a time.  Rows past the end re-read row n-1 and write
+// it again (the same value to the same place), so no write is guarded.  Row
+// offsets are 24-bit products: ld < 2^24 (at most N (N-1) (N-2) < 2^18 for
+// N <= 64) and the offsets stay below 2^32 bytes.
 constexpr int kStageRows = 24;
 constexpr int kStageTail = 8;
 
@@ -43,27 +45,29 @@ template <typename T, int SEG, int K>
 __device__ __forceinline__ void stage_block(T* __restrict__ M, const T* __restrict__ blk, long long ld, int n,
                                             int lane)
 {
-    const int ldi = (int)ld;
+    const unsigned ldb = (unsigned)ld * (unsigned)sizeof(T);   // row stride in bytes (< 2^24 * 8)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int c = lane + k * SEG;
         if (c < n) {
-            const T* __restrict__ col = blk + c;
+            const char* __restrict__ col = reinterpret_cast<const char*>(blk + c);
+            auto row_at = [&](int r) -> T {
+                return *reinterpret_cast<const T*>(col + (size_t)(unsigned)__umul24((unsigned)r, ldb));
+            };
             {
                 T t[kStageRows];
 #pragma unroll
-                for (int u = 0; u < kStageRows; ++u) t[u] = col[min(u, n - 1) * ldi];
+                for (int u = 0; u < kStageRows; ++u) t[u] = row_at(min(u, n - 1));
 #pragma unroll
-                for (int u = 0; u < kStageRows; ++u)
-                    if (u < n) M[u * n + c] = t[u];
+                for (int u = 0; u < kStageRows; ++u) M[__umul24((unsigned)min(u, n - 1), (unsigned)n) + c] = t[u];
             }
             for (int r0 = kStageRows; r0 < n; r0 += kStageTail) {
                 T t[kStageTail];
 #pragma unroll
-                for (int u = 0; u < kStageTail; ++u) t[u] = col[min(r0 + u, n - 1) * ldi];
+                for (int u = 0; u < kStageTail; ++u) t[u] = row_at(min(r0 + u, n - 1));
 #pragma unroll
                 for (int u = 0; u < kStageTail; ++u)
-                    if (r0 + u < n) M[(r0 + u) * n + c] = t[u];
+                    M[__umul24((unsigned)min(r0 + u, n - 1), (unsigned)n) + c] = t[u];
             }
         }
     }

@@ -465,21 +465,22 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
     // Each loop reads kReduceChunk LDS entries before it uses any of them
     // (indices past n - 1 re-read entry n - 1, which changes no minimum and
     // sets no new bit), so a lane waits for LDS once per chunk.  Zero masks are
-    // 32-bit when a problem has at most 32 columns.
+    // 32-bit when a problem has at most 32 columns.  The minima are kept with
+    // selects rather than branches (the first of equal values stays), and row
+    // offsets are 24-bit products (n <= 64).
     constexpr int kReduceChunk = 8;
     using Mask = std::conditional_t<(SEG * K <= 32), unsigned, unsigned long long>;
     const T* __restrict__ M = sc.M;
     for (int s = 0; s < K; ++s) {
         if (!ok[s]) continue;
-        const T* __restrict__ Mr = M + c[s] * n;
+        const T* __restrict__ Mr = M + __umul24(c[s], n);
         T um = Mr[0];
         for (int q0 = 0; q0 < n; q0 += kReduceChunk) {
             T m[kReduceChunk];
 #pragma unroll
             for (int e = 0; e < kReduceChunk; ++e) m[e] = Mr[min(q0 + e, n - 1)];
 #pragma unroll
-            for (int e = 0; e < kReduceChunk; ++e)
-                if (m[e] < um) um = m[e];
+            for (int e = 0; e < kReduceChunk; ++e) um = m[e] < um ? m[e] : um;
         }
         sc.vb[c[s]] = (double)um;
     }
@@ -490,24 +491,22 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
         row[s] = -1;
         zc[s] = 0;
         if (!ok[s]) continue;
-        T vm = M[c[s]] - (T)sc.vb[0];
+        const T* __restrict__ Mc = M + c[s];
+        T vm = Mc[0] - (T)sc.vb[0];
         Mask z = 1;
         for (int r0 = 0; r0 < n; r0 += kReduceChunk) {
             T x[kReduceChunk];
 #pragma unroll
             for (int e = 0; e < kReduceChunk; ++e) {
                 const int r = min(r0 + e, n - 1);
-                x[e] = M[r * n + c[s]] - (T)sc.vb[r];
+                x[e] = Mc[__umul24(r, n)] - (T)sc.vb[r];
             }
 #pragma unroll
             for (int e = 0; e < kReduceChunk; ++e) {
-                const int r = min(r0 + e, n - 1);
-                if (x[e] < vm) {
-                    vm = x[e];
-                    z = Mask(1) << r;
-                } else if (x[e] == vm) {
-                    z |= Mask(1) << r;
-                }
+                const Mask bit = Mask(1) << min(r0 + e, n - 1);
+                const bool lt = x[e] < vm, eq = x[e] == vm;
+                z = lt ? bit : (eq ? (z | bit) : z);
+                vm = lt ? x[e] : vm;
             }
         }
         v[s] = vm;
@@ -515,11 +514,11 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
     }
     if constexpr (K == 1) {
         // One column per lane: the greedy matching runs on the scalar unit,
-        // each segment's column q read from its lane q, and that lane takes
-        // the chosen row.
+        // each segment's column q read from its lane q.  The rows taken before
+        // column q are written to lane q, which afterwards takes the lowest of
+        // its zero rows outside that set (the row the scalar loop gave it).
         constexpr int LPW = 64 / SEG;
         const int seg = (threadIdx.x & 63) / SEG;
-        int rowv = -1;
         Mask tk[LPW];
         int ns[LPW];
         int nmax = 0;
@@ -529,26 +528,30 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
             ns[g] = __builtin_amdgcn_readlane(n, g * SEG);
             nmax = ::max(nmax, ns[g]);
         }
+        const int wl = threadIdx.x & 63;
+        Mask before = 0;   // rows taken before this lane's column
         for (int q = 0; q < nmax; ++q) {
 #pragma unroll
             for (int g = 0; g < LPW; ++g) {
                 if (q >= ns[g]) continue;
+                const int ln = g * SEG + q;
                 Mask z;
                 if constexpr (sizeof(Mask) == 4) {
-                    z = (Mask)__builtin_amdgcn_readlane((int)zc[0], g * SEG + q);
+                    z = (Mask)__builtin_amdgcn_readlane((int)zc[0], ln);
                 } else {
-                    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)zc[0], g * SEG + q);
-                    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(zc[0] >> 32), g * SEG + q);
+                    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)zc[0], ln);
+                    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(zc[0] >> 32), ln);
                     z = ((Mask)hi << 32) | lo;
                 }
+                before = wl == ln ? tk[g] : before;
                 z &= ~tk[g];
-                if (z) {
-                    const int r = sizeof(Mask) == 4 ? __builtin_ctz((unsigned)z) : __builtin_ctzll((unsigned long long)z);
-                    tk[g] |= Mask(1) << r;
-                    if ((int)(threadIdx.x & 63) == g * SEG + q) rowv = r;
-                }
+                tk[g] |= z & (Mask(0) - z);   // its lowest set bit
             }
         }
+        const Mask mine = zc[0] & ~before;
+        const int rowv = mine ? (sizeof(Mask) == 4 ? __builtin_ctz((unsigned)mine)
+                                                   : __builtin_ctzll((unsigned long long)mine))
+                              : -1;
         row[0] = ok[0] ? rowv : -1;
         Mask taken = tk[0];
 #pragma unroll
@@ -762,12 +765,20 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
     const T* __restrict__ M = sc.M;
     const int l = threadIdx.x & (SEG - 1);
     const T INF = inf_of<T>();
-    // sigma (column of each row) and v in LDS.
-    const int prow = poff >= 0 ? poff / n : -1;
-    if (l < n && prow >= 0 && prow < n) sc.aux[prow] = l;
+    // sigma (column of each row) and v in LDS; sigma also as 16-bit keys in
+    // sc.way, right after the column pass's keys sc.p (the row offsets), so
+    // both passes read their key with one load.  prow = poff / n: poff = r n
+    // with r < 64, and the reciprocal's relative error (a few 2^-24) moves
+    // r by far less than 1/2.
+    const int prow = poff >= 0 ? (int)__builtin_rintf((float)poff * __builtin_amdgcn_rcpf((float)n)) : -1;
+    if (l < n && prow >= 0 && prow < n) {
+        sc.aux[prow] = l;
+        sc.way[prow] = (short)l;
+    }
     if (l < n) sc.vb[l] = (double)v;
     wave_sync();
     const bool rowpass = l >= H;
+    const short* __restrict__ keys = rowpass ? sc.way : sc.p;
     const int h = l & (H - 1);
     int t[2], base[2];
     T lab[2], w[2];
@@ -789,17 +800,19 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
         // pass: K = offset of p(f); row pass: K = sigma(f)) is M[base + K].
         base[q] = rowpass ? tc * n : tc;
     }
+    // Branch-free steps: every node's relaxation is computed (the entry read
+    // for a fixed or absent node is in range and its result is discarded).
     for (int step = 0; step < n; ++step) {
         const T dmin = HS::min(tmin(fx[0] ? INF : lab[0], fx[1] ? INF : lab[1]));
         const int cand = (!fx[0] && lab[0] == dmin) ? t[0] : ((!fx[1] && lab[1] == dmin) ? t[1] : NONE);
         const int f = HS::imin(cand);
         const int fc = f < n ? f : 0;
-        const int key = rowpass ? sc.aux[fc] : (int)sc.p[fc];
+        const int key = keys[fc];
         const T s1 = rowpass ? (T)sc.vb[key] : (T)sc.u[fc];
         for (int q = 0; q < 2; ++q) {
             fx[q] = fx[q] || (t[q] == f);
             const T nd = dmin + ((M[base[q] + key] - s1) - w[q]);
-            if (!fx[q] && nd < lab[q]) lab[q] = nd;
+            lab[q] = (!fx[q] && nd < lab[q]) ? nd : lab[q];
         }
     }
     wave_sync();
@@ -855,7 +868,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
         int rw[1];
         const unsigned long long taken = lap_reduce_start<T, SEG, 1>(sc, n, cl, okl, va, rw);
         v = va[0];
-        poff = rw[0] >= 0 ? rw[0] * n : -1;
+        poff = rw[0] >= 0 ? __umul24(rw[0], n) : -1;
         ucol = rw[0] >= 0 ? (T)sc.vb[rw[0]] : (T)0;
         if (ok) {
             sc.p[l] = poff;
@@ -871,7 +884,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
     T dist = INF;
     int way = -1;
     bool used = false;
-    int i0n = row >= 0 ? row * n : 0;   // offset of the row being scanned
+    int i0n = row >= 0 ? __umul24(row, n) : 0;   // offset of the row being scanned
     T urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;   // dual of the free row being inserted
     T ui0 = urow0;                                // dual of the row being scanned
     T d0 = 0;
@@ -880,10 +893,9 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
         const bool active = row >= 0;
         const bool live = active && ok && !used;
         const T cur = d0 + ((M[i0n + (ok ? l : 0)] - ui0) - v);
-        if (live && cur < dist) {
-            dist = cur;
-            way = j0;
-        }
+        const bool better = live && cur < dist;
+        dist = better ? cur : dist;
+        way = better ? j0 : way;
         const T lm = live ? dist : INF;
         const T dmin = S::min(lm);
         const int j1 = Bits::first(Bits::get(live && lm == dmin));
@@ -927,7 +939,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
                     j = sc.way[j];
                 }
                 if (onpath) {
-                    newp = way >= 0 ? pw : row * n;
+                    newp = way >= 0 ? pw : __umul24(row, n);
                     newu = way >= 0 ? uw : urow0 + dmin;
                 }
             }
@@ -944,7 +956,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
                 dist = INF;
                 way = -1;
                 used = false;
-                i0n = row >= 0 ? row * n : 0;
+                i0n = row >= 0 ? __umul24(row, n) : 0;
                 urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;
                 ui0 = urow0;
                 d0 = 0;
@@ -998,12 +1010,16 @@ __device__ __forceinline__ void canonical_split_k(const SlotScratch<T, SEG, K>& 
     for (int s = 0; s < K; ++s) {
         const int c = s * SEG + l;
         if (c >= n) continue;
-        const int prow = poff[s] >= 0 ? poff[s] / n : -1;
-        if (prow >= 0 && prow < n) sc.aux[prow] = c;
+        const int prow = poff[s] >= 0 ? (int)__builtin_rintf((float)poff[s] * __builtin_amdgcn_rcpf((float)n)) : -1;
+        if (prow >= 0 && prow < n) {
+            sc.aux[prow] = c;
+            sc.way[prow] = (short)c;
+        }
         sc.vb[c] = (double)v[s];
     }
     wave_sync();
     const bool rowpass = l >= H;
+    const short* __restrict__ keys = rowpass ? sc.way : sc.p;
     const int h = l & (H - 1);
     int t[NQ], base[NQ];
     T lab[NQ], w[NQ];
@@ -1032,12 +1048,12 @@ __device__ __forceinline__ void canonical_split_k(const SlotScratch<T, SEG, K>& 
             if (!fx[q] && lab[q] == dmin) cand = t[q];
         const int f = HS::imin(cand);
         const int fc = f < n ? f : 0;
-        const int key = rowpass ? sc.aux[fc] : (int)sc.p[fc];
+        const int key = keys[fc];
         const T s1 = rowpass ? (T)sc.vb[key] : (T)sc.u[fc];
         for (int q = 0; q < NQ; ++q) {
             fx[q] = fx[q] || (t[q] == f);
             const T nd = dmin + ((M[base[q] + key] - s1) - w[q]);
-            if (!fx[q] && nd < lab[q]) lab[q] = nd;
+            lab[q] = (!fx[q] && nd < lab[q]) ? nd : lab[q];
         }
     }
     wave_sync();
@@ -1094,7 +1110,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
         int rw[K];
         const unsigned long long taken = lap_reduce_start<T, SEG, K>(sc, n, c, ok, v, rw);
         for (int s = 0; s < K; ++s) {
-            poff[s] = rw[s] >= 0 ? rw[s] * n : -1;
+            poff[s] = rw[s] >= 0 ? __umul24(rw[s], n) : -1;
             ucol[s] = rw[s] >= 0 ? (T)sc.vb[rw[s]] : (T)0;
         }
         freem = ~taken & (n >= 64 ? ~0ull : ((1ull << n) - 1ull));
@@ -1118,7 +1134,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
         way[s] = -1;
         used[s] = false;
     }
-    int i0n = row >= 0 ? row * n : 0;
+    int i0n = row >= 0 ? __umul24(row, n) : 0;
     T urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;
     T ui0 = urow0;
     T d0 = 0;
@@ -1130,10 +1146,9 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
         for (int s = 0; s < K; ++s) {
             live[s] = active && ok[s] && !used[s];
             const T cur = d0 + ((M[i0n + (ok[s] ? c[s] : 0)] - ui0) - v[s]);
-            if (live[s] && cur < dist[s]) {
-                dist[s] = cur;
-                way[s] = j0;
-            }
+            const bool better = live[s] && cur < dist[s];
+            dist[s] = better ? cur : dist[s];
+            way[s] = better ? j0 : way[s];
             lm[s] = live[s] ? dist[s] : INF;
         }
         T lmin = lm[0];
@@ -1184,7 +1199,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
                 for (int s = 0; s < K; ++s) {
                     if (!onpath[s]) continue;
                     const int wc = way[s] >= 0 ? way[s] : 0;
-                    newp[s] = way[s] >= 0 ? (int)sc.p[wc] : row * n;
+                    newp[s] = way[s] >= 0 ? (int)sc.p[wc] : __umul24(row, n);
                     newu[s] = way[s] >= 0 ? (T)sc.u[wc] : urow0 + dmin;
                 }
             }
@@ -1203,7 +1218,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
                 }
                 row = freem ? __builtin_ctzll(freem) : -1;
                 freem &= freem - 1;
-                i0n = row >= 0 ? row * n : 0;
+                i0n = row >= 0 ? __umul24(row, n) : 0;
                 urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;
                 ui0 = urow0;
                 d0 = 0;

@@ -212,26 +212,46 @@ __host__ __device__ __forceinline__ long long pair_row(int N, int a, int la, int
 // *beta gets the block number (position of its c in C), *twin that of its
 // complement and *base the offset of its first row (rows are
 // N (N-1) (N-2) apart).
+// The quotients are taken in FP32 and corrected once: h < N^2 (N-1)^2 / 2 <
+// 2^23 for N <= 64 is exact in FP32 and the computed quotient is within
+// 2^-22 relative (less than 1/2) of the true one.  Facility a of pair index
+// P is the largest a with S(a) = a (2N - a - 1) / 2 <= P, from the root of
+// that quadratic, corrected the same way.
 __host__ __device__ __forceinline__ void pair_block(int N, long long h, long long* beta, long long* twin,
                                                     long long* base)
 {
-    // h < N^2 (N-1)^2 / 2 < 2^23 for N <= 64: 32-bit arithmetic
     const int n1 = N - 1;
     const int NL = N * n1;
     const int hh = (int)h;
-    int P = hh / NL;
-    const int L = hh - P * NL;
-    *base = ((long long)P * (N - 2) * NL + L) * (N - 2);
-    int a = 0;
-    while (P >= n1 - a) {
-        P -= n1 - a;
-        ++a;
+    int P = (int)((float)hh * (1.0f / (float)NL));
+    int L = hh - P * NL;
+    if (L < 0) {
+        --P;
+        L += NL;
+    } else if (L >= NL) {
+        ++P;
+        L -= NL;
     }
-    const int b = a + 1 + P;
-    const int la = L / n1, lq = L % n1;
+    // 32-bit products up to the last multiplication (block numbers are below
+    // N^2 (N-1)^2 < 2^24); the first-row offset needs 64 bits.
+    *base = (long long)(((unsigned long long)(unsigned)(P * (N - 2)) * (unsigned)NL + (unsigned)L) * (unsigned)(N - 2));
+    const float tw = (float)(2 * N - 1);
+    int a = (int)((tw - sqrtf(tw * tw - 8.0f * (float)P)) * 0.5f);
+    if (a * (2 * N - a - 1) / 2 > P) --a;
+    else if ((a + 1) * (2 * N - a - 2) / 2 <= P) ++a;
+    const int b = a + 1 + (P - a * (2 * N - a - 1) / 2);
+    int la = (int)((float)L * (1.0f / (float)n1));
+    int lq = L - la * n1;
+    if (lq < 0) {
+        --la;
+        lq += n1;
+    } else if (lq >= n1) {
+        ++la;
+        lq -= n1;
+    }
     const int lb = lq + (lq >= la);
-    *beta = ((long long)(a * N + la) * n1 + (b - 1)) * n1 + lq;
-    *twin = ((long long)(b * N + lb) * n1 + a) * n1 + (la - (la > lb));
+    *beta = ((a * N + la) * n1 + (b - 1)) * n1 + lq;
+    *twin = ((b * N + lb) * n1 + a) * n1 + (la - (la > lb));
 }
 
 // Offset of d_{(a,la),(b,lb),(c,lc)} inside block beta_of(a,la,b,lb).
