@@ -65,6 +65,7 @@ __device__ __forceinline__ double lap_auction_flat(const SlotScratch<T, SEG, 1>&
 {
     using S = SegS<SEG>;
     const T* __restrict__ M = sc.M;
+    const int ldm = sc.ld;   // row stride of M
     const int l = S::lane();
     const bool ok = l < n;
     double* __restrict__ price = sc.u;
@@ -75,7 +76,7 @@ __device__ __forceinline__ double lap_auction_flat(const SlotScratch<T, SEG, 1>&
     // Scale of the problem: the largest |M_rq|.
     double big = 0.0;
     if (ok)
-        for (int q = 0; q < n; ++q) big = __builtin_fmax(big, __builtin_fabs((double)M[l * n + q]));
+        for (int q = 0; q < n; ++q) big = __builtin_fmax(big, __builtin_fabs((double)M[l * ldm + q]));
     big = -S::min(-big);
     if (ok) price[l] = 0.0;
     int my = -1;   // object held by person l
@@ -101,7 +102,7 @@ __device__ __forceinline__ double lap_auction_flat(const SlotScratch<T, SEG, 1>&
             unsigned long long mk = 0ull;
             if (bidding) {
                 double w1 = __builtin_huge_val(), w2 = __builtin_huge_val();
-                const T* __restrict__ Mr = M + l * n;
+                const T* __restrict__ Mr = M + l * ldm;
                 for (int q = 0; q < n; ++q) {
                     const double val = (double)Mr[q] + price[q];
                     if (val < w1) {
@@ -150,7 +151,7 @@ __device__ __forceinline__ double lap_auction_flat(const SlotScratch<T, SEG, 1>&
     T urow = (T)0, vcol = (T)0;
     if (ok) {
         double u = __builtin_huge_val();
-        for (int q = 0; q < n; ++q) u = __builtin_fmin(u, (double)M[l * n + q] + price[q]);
+        for (int q = 0; q < n; ++q) u = __builtin_fmin(u, (double)M[l * ldm + q] + price[q]);
         urow = (T)u;
         vcol = (T)(-price[l]);
     }

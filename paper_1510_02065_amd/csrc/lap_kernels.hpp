@@ -31,7 +31,7 @@ enum DStorage : int {
 };
 
 // Copy an n x n block (row stride ld in global memory) into LDS (row stride
-// n).  Each lane issues the loads of a whole chunk of rows before it writes
+// ldm).  Each lane issues the loads of a whole chunk of rows before it writes
 // any of them, so a wave waits for HBM once per chunk instead of once per row:
 // the first kStageRows rows (all of them up to n = 24) in straight-line code,
 // the rest kStageTail at a time.  Rows past the end re-read row n-1 and write
@@ -42,8 +42,8 @@ constexpr int kStageRows = 24;
 constexpr int kStageTail = 8;
 
 template <typename T, int SEG, int K>
-__device__ __forceinline__ void stage_block(T* __restrict__ M, const T* __restrict__ blk, long long ld, int n,
-                                            int lane)
+__device__ __forceinline__ void stage_block(T* __restrict__ M, int ldm, const T* __restrict__ blk, long long ld,
+                                            int n, int lane)
 {
     const unsigned ldb = (unsigned)ld * (unsigned)sizeof(T);   // row stride in bytes (< 2^24 * 8)
 #pragma unroll
@@ -59,7 +59,7 @@ __device__ __forceinline__ void stage_block(T* __restrict__ M, const T* __restri
 #pragma unroll
                 for (int u = 0; u < kStageRows; ++u) t[u] = row_at(min(u, n - 1));
 #pragma unroll
-                for (int u = 0; u < kStageRows; ++u) M[__umul24((unsigned)min(u, n - 1), (unsigned)n) + c] = t[u];
+                for (int u = 0; u < kStageRows; ++u) M[__umul24((unsigned)min(u, n - 1), (unsigned)ldm) + c] = t[u];
             }
             for (int r0 = kStageRows; r0 < n; r0 += kStageTail) {
                 T t[kStageTail];
@@ -67,7 +67,7 @@ __device__ __forceinline__ void stage_block(T* __restrict__ M, const T* __restri
                 for (int u = 0; u < kStageTail; ++u) t[u] = row_at(min(r0 + u, n - 1));
 #pragma unroll
                 for (int u = 0; u < kStageTail; ++u)
-                    M[__umul24((unsigned)min(r0 + u, n - 1), (unsigned)n) + c] = t[u];
+                    M[__umul24((unsigned)min(r0 + u, n - 1), (unsigned)ldm) + c] = t[u];
             }
         }
     }
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(64) void k_lap_family_s(StoreT<PM>* __restrict__ D,
         }
     }
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
-    stage_block<T, SEG, K>(sc.M, blk, ld, n, lane);
+    stage_block<T, SEG, K>(sc.M, sc.ld, blk, ld, n, lane);
     wave_sync();
     double S;
     static_assert(!AUC || K == 1, "the auction solver takes one column per lane");
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(64) void k_lap_B_s(StoreT<PM>* __restrict__ B, cons
     const int n = active ? I.N : 0;
     T* blk = B + I.offB;
     const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
-    stage_block<T, SEG, K>(sc.M, blk, n, n, lane);
+    stage_block<T, SEG, K>(sc.M, sc.ld, blk, n, n, lane);
     wave_sync();
     int32_t* sg = (active && sigma) ? sigma + I.offB : nullptr;
     double S;
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(64) void k_lap_batch(int count, const int* __restri
     const SlotScratch<T, SEG, 1> sc(smem + seg * SlotLds<T, SEG, 1>::bytes(SEG), n);
     T* mat = (in && !bad) ? cost + mat_off[b] : nullptr;
     const int64_t vo = (in && !bad && vec_off) ? vec_off[b] : 0;
-    stage_block<T, SEG, 1>(sc.M, mat, n, n, lane);
+    stage_block<T, SEG, 1>(sc.M, sc.ld, mat, n, n, lane);
     wave_sync();
     T* const Rw = (write_residual && n > 0) ? mat : nullptr;
     T* const dw = (duals && n > 0) ? duals + 4 * vo : nullptr;

@@ -128,16 +128,20 @@ __device__ __forceinline__ T tree_sum64(const T (&x)[K], Add add)
 }
 
 // Per-problem LDS working set, for a problem of size n:
-// [matrix n*n of T | aux: n ints | p: n shorts | way: n shorts | pad |
-//  u: n doubles | vb: n doubles].  The LDS a wave needs bounds how many
+// [matrix n x n of T, row stride ld = n | 1 | aux: n ints | p: n shorts |
+//  way: n shorts | pad | u: n doubles | vb: n doubles].  The odd row stride
+// puts the rows a lane-per-row access reads (lane r reading row r) on
+// distinct LDS banks; with an even n, lanes whose rows lie a multiple of
+// 64 / gcd(n, 64) banks' worth apart would hit the same bank.  The LDS a wave needs bounds how many
 // waves a CU holds, and the assignment kernels run faster the more it holds,
 // so the arrays hold the n columns only (every write is guarded by c < n),
 // row and path indices (< 64 * 64) are 16-bit, and no array is kept that
 // another one can stand in for.
 template <typename T, int SEG, int K>
 struct SlotLds {
+    __host__ __device__ static int row_stride(int n) { return n | 1; }
     __host__ __device__ static size_t mat_bytes(int n) {
-        return (((size_t)n * n * sizeof(T)) + 15) & ~(size_t)15;
+        return (((size_t)n * row_stride(n) * sizeof(T)) + 15) & ~(size_t)15;
     }
     __host__ __device__ static size_t idx_bytes(int n) {
         return (((size_t)n * sizeof(int) + 2 * (size_t)n * sizeof(short)) + 15) & ~(size_t)15;
@@ -149,14 +153,16 @@ struct SlotLds {
 template <typename T, int SEG, int K>
 struct SlotScratch {
     T* M;
+    int ld;      // row stride of M (odd)
     int* aux;    // row ownership, then sigma (column of row r)
-    short* p;    // row matched to column c (or -1); the flat solver keeps r*n
+    short* p;    // row matched to column c (or -1); the flat solver keeps r*ld
     short* way;  // predecessor column on the shortest path
     double* u;   // dual of the row matched to column c; scratch in the completion
     double* vb;  // column duals in the canonical passes; scratch in the completion
     __device__ SlotScratch(unsigned char* base, int n) {
         const size_t mb = SlotLds<T, SEG, K>::mat_bytes(n);
         M = reinterpret_cast<T*>(base);
+        ld = SlotLds<T, SEG, K>::row_stride(n);
         aux = reinterpret_cast<int*>(base + mb);
         p = reinterpret_cast<short*>(aux + n);
         way = p + n;
@@ -183,6 +189,7 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
     using S = SegS<SEG>;
     constexpr int NONE = 1 << 20;   // larger than any column index
     const T* __restrict__ M = sc.M;
+    const int ldm = sc.ld;   // row stride of M
     const int lane = S::lane();
     const T INF = inf_of<T>();
     int c[K];
@@ -217,7 +224,7 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
             const T ur = (T)sc.u[cc];
             for (int s = 0; s < K; ++s) {
                 done[s] = done[s] || (c[s] == cc);
-                const T nd = dmin + ((M[r * n + (ok[s] ? c[s] : 0)] - ur) - v[s]);
+                const T nd = dmin + ((M[r * ldm + (ok[s] ? c[s] : 0)] - ur) - v[s]);
                 if (!done[s] && nd < x[s]) x[s] = nd;
             }
         }
@@ -265,7 +272,7 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
             const T vcs = (T)sc.vb[cs];
             for (int s = 0; s < K; ++s) {
                 done[s] = done[s] || (c[s] == rr);
-                const T nd = dmin + ((M[(ok[s] ? c[s] : 0) * n + cs] - vcs) - urow[s]);
+                const T nd = dmin + ((M[(ok[s] ? c[s] : 0) * ldm + cs] - vcs) - urow[s]);
                 if (!done[s] && nd < y[s]) y[s] = nd;
             }
         }
@@ -294,6 +301,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
 {
     using S = SegS<SEG>;
     const T* __restrict__ M = sc.M;
+    const int ldm = sc.ld;   // row stride of M
     const int lane = S::lane();
     const T INF = inf_of<T>();
     int c[K];
@@ -318,8 +326,8 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             uc[s] = INF;
             vr[s] = INF;
             if (ok[s]) {
-                for (int q = 0; q < n; ++q) uc[s] = tmin(uc[s], M[c[s] * n + q] - (T)sc.u[q]);
-                for (int r = 0; r < n; ++r) vr[s] = tmin(vr[s], M[r * n + c[s]] - (T)sc.vb[r]);
+                for (int q = 0; q < n; ++q) uc[s] = tmin(uc[s], M[c[s] * ldm + q] - (T)sc.u[q]);
+                for (int r = 0; r < n; ++r) vr[s] = tmin(vr[s], M[r * ldm + c[s]] - (T)sc.vb[r]);
             }
         }
         wave_sync();
@@ -331,7 +339,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
                 if (!ok[s]) continue;
                 T* Rr = R + c[s];
                 for (int r = 0; r < n; ++r, Rr += ldr) {
-                    const T m = M[r * n + c[s]];
+                    const T m = M[r * ldm + c[s]];
                     const T r1 = (m - vc[s]) - (T)sc.u[r];
                     const T r2 = (m - (T)sc.vb[r]) - vr[s];
                     *Rr = (T)0.5 * (r1 + r2);
@@ -391,9 +399,9 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             vr[s] = __builtin_huge_val();
             if (ok[s]) {
                 for (int q = 0; q < n; ++q)
-                    uc[s] = __builtin_fmin(uc[s], (double)M[c[s] * n + q] - sc.u[q]);
+                    uc[s] = __builtin_fmin(uc[s], (double)M[c[s] * ldm + q] - sc.u[q]);
                 for (int r = 0; r < n; ++r)
-                    vr[s] = __builtin_fmin(vr[s], (double)M[r * n + c[s]] - sc.vb[r]);
+                    vr[s] = __builtin_fmin(vr[s], (double)M[r * ldm + c[s]] - sc.vb[r]);
                 uc[s] -= __builtin_fabs(uc[s]) * 0x1p-50;
                 vr[s] -= __builtin_fabs(vr[s]) * 0x1p-50;
             }
@@ -409,7 +417,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
                 if (!ok[s]) continue;
                 T* Rr = R + c[s];
                 for (int r = 0; r < n; ++r, Rr += ldr) {
-                    const double m = (double)M[r * n + c[s]];
+                    const double m = (double)M[r * ldm + c[s]];
                     const double ur_ = sc.u[r];
                     const double t = (m - V[s]) - ur_;
                     const double margin = ((__builtin_fabs(m) + __builtin_fabs(V[s])) + __builtin_fabs(ur_)) * 0x1p-50;
@@ -471,9 +479,10 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
     constexpr int kReduceChunk = 8;
     using Mask = std::conditional_t<(SEG * K <= 32), unsigned, unsigned long long>;
     const T* __restrict__ M = sc.M;
+    const int ldm = sc.ld;   // row stride of M
     for (int s = 0; s < K; ++s) {
         if (!ok[s]) continue;
-        const T* __restrict__ Mr = M + __umul24(c[s], n);
+        const T* __restrict__ Mr = M + __umul24(c[s], ldm);
         T um = Mr[0];
         for (int q0 = 0; q0 < n; q0 += kReduceChunk) {
             T m[kReduceChunk];
@@ -499,7 +508,7 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
 #pragma unroll
             for (int e = 0; e < kReduceChunk; ++e) {
                 const int r = min(r0 + e, n - 1);
-                x[e] = Mc[__umul24(r, n)] - (T)sc.vb[r];
+                x[e] = Mc[__umul24(r, ldm)] - (T)sc.vb[r];
             }
 #pragma unroll
             for (int e = 0; e < kReduceChunk; ++e) {
@@ -601,6 +610,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
     using S = SegS<SEG>;
     constexpr int NONE = 1 << 20;   // larger than any column index
     const T* __restrict__ M = sc.M;
+    const int ldm = sc.ld;   // row stride of M
     const int lane = S::lane();
     const T INF = inf_of<T>();
 
@@ -648,7 +658,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
             int lc = NONE;
             for (int s = 0; s < K; ++s) {
                 const bool live = ok[s] && !used[s];
-                const T cur = d0 + ((M[i0 * n + (ok[s] ? c[s] : 0)] - ui0) - v[s]);
+                const T cur = d0 + ((M[i0 * ldm + (ok[s] ? c[s] : 0)] - ui0) - v[s]);
                 if (live && cur < dist[s]) {
                     dist[s] = cur;
                     way[s] = j0;
@@ -752,7 +762,7 @@ struct SegBits {
 // their lowest candidate index.  On return (lane as column / as row, K = 1
 // layout) vc is the column-canonical dual of the lane's column, ur the
 // row-canonical dual of its row and sg its row's column.  Expects sc.p
-// (offset r*n of the row matched to each column) and sc.u (that row's dual);
+// (offset r*ld of the row matched to each column) and sc.u (that row's dual);
 // poff is this lane's.
 template <typename T, int SEG>
 __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc, int n, T v, int poff, T& vc,
@@ -763,14 +773,15 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
     constexpr int NONE = 1 << 20;
     using HS = SegS<H>;
     const T* __restrict__ M = sc.M;
+    const int ldm = sc.ld;   // row stride of M
     const int l = threadIdx.x & (SEG - 1);
     const T INF = inf_of<T>();
     // sigma (column of each row) and v in LDS; sigma also as 16-bit keys in
     // sc.way, right after the column pass's keys sc.p (the row offsets), so
-    // both passes read their key with one load.  prow = poff / n: poff = r n
+    // both passes read their key with one load.  prow = poff / ld: poff = r ld
     // with r < 64, and the reciprocal's relative error (a few 2^-24) moves
     // r by far less than 1/2.
-    const int prow = poff >= 0 ? (int)__builtin_rintf((float)poff * __builtin_amdgcn_rcpf((float)n)) : -1;
+    const int prow = poff >= 0 ? (int)__builtin_rintf((float)poff * __builtin_amdgcn_rcpf((float)ldm)) : -1;
     if (l < n && prow >= 0 && prow < n) {
         sc.aux[prow] = l;
         sc.way[prow] = (short)l;
@@ -798,7 +809,7 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
         fx[q] = !okn;
         // M entry of node t relaxed through a fixed node with key K (column
         // pass: K = offset of p(f); row pass: K = sigma(f)) is M[base + K].
-        base[q] = rowpass ? tc * n : tc;
+        base[q] = rowpass ? tc * ldm : tc;
     }
     // Branch-free steps: every node's relaxation is computed (the entry read
     // for a fixed or absent node is in range and its result is discarded).
@@ -842,7 +853,7 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
 // busiest problem needs rather than the sum over rows of the busiest problem
 // per row.  The argmin is a ballot of the lanes at the minimum (the lowest
 // such lane is the lowest column), and the matched rows are kept in LDS as row
-// offsets r * n.  The decisions and the arithmetic are those of
+// offsets r * ld.  The decisions and the arithmetic are those of
 // lap_concentrate_slots.
 template <typename T, int SEG, bool DOWN>
 __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG, 1>& sc, int n,
@@ -852,13 +863,14 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
     using S = SegS<SEG>;
     using Bits = SegBits<SEG>;
     const T* __restrict__ M = sc.M;
+    const int ldm = sc.ld;   // row stride of M
     const int l = S::lane();
     const bool ok = l < n;
     const T INF = inf_of<T>();
 
     // ---- two-sided reduction and greedy start -------------------------------
     T v;
-    int poff;   // offset r * n of the matched row, -1 when free
+    int poff;   // offset r * ld of the matched row, -1 when free
     T ucol;     // dual of that row
     unsigned long long freem;   // free rows (bit r)
     {
@@ -868,7 +880,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
         int rw[1];
         const unsigned long long taken = lap_reduce_start<T, SEG, 1>(sc, n, cl, okl, va, rw);
         v = va[0];
-        poff = rw[0] >= 0 ? __umul24(rw[0], n) : -1;
+        poff = rw[0] >= 0 ? __umul24(rw[0], ldm) : -1;
         ucol = rw[0] >= 0 ? (T)sc.vb[rw[0]] : (T)0;
         if (ok) {
             sc.p[l] = poff;
@@ -884,7 +896,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
     T dist = INF;
     int way = -1;
     bool used = false;
-    int i0n = row >= 0 ? __umul24(row, n) : 0;   // offset of the row being scanned
+    int i0n = row >= 0 ? __umul24(row, ldm) : 0;   // offset of the row being scanned
     T urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;   // dual of the free row being inserted
     T ui0 = urow0;                                // dual of the row being scanned
     T d0 = 0;
@@ -939,7 +951,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
                     j = sc.way[j];
                 }
                 if (onpath) {
-                    newp = way >= 0 ? pw : __umul24(row, n);
+                    newp = way >= 0 ? pw : __umul24(row, ldm);
                     newu = way >= 0 ? uw : urow0 + dmin;
                 }
             }
@@ -956,7 +968,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
                 dist = INF;
                 way = -1;
                 used = false;
-                i0n = row >= 0 ? __umul24(row, n) : 0;
+                i0n = row >= 0 ? __umul24(row, ldm) : 0;
                 urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;
                 ui0 = urow0;
                 d0 = 0;
@@ -976,7 +988,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
         return lap_complete<T, SEG, 1, DOWN>(sc, n, R, ldr, duals, assign, vca, ura, sga);
     } else {
         // Row indices for the sequential canonical passes.
-        const int prow = poff >= 0 ? poff / n : -1;
+        const int prow = poff >= 0 ? poff / ldm : -1;
         if (ok) sc.p[l] = prow;
         wave_sync();
         const T va[1] = {v};
@@ -991,7 +1003,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
 // each lane holding the 2K nodes h, h + SEG/2, ..., h + (2K-1) SEG/2.  Same
 // decisions and operations as canonical_split (and lap_canonical_finish):
 // the lowest node at the minimum, relaxations (M - per-step dual) - per-node
-// dual.  poff[s] is the offset r*n of the row matched to column c_s (-1 when
+// dual.  poff[s] is the offset r*ld of the row matched to column c_s (-1 when
 // none); on return vc, ur and sg hold, for each of the lane's columns c_s
 // (rows c_s), the column-canonical dual, the row-canonical dual and the
 // row's column.
@@ -1005,12 +1017,13 @@ __device__ __forceinline__ void canonical_split_k(const SlotScratch<T, SEG, K>& 
     constexpr int NONE = 1 << 20;
     using HS = SegS<H>;
     const T* __restrict__ M = sc.M;
+    const int ldm = sc.ld;   // row stride of M
     const int l = threadIdx.x & (SEG - 1);
     const T INF = inf_of<T>();
     for (int s = 0; s < K; ++s) {
         const int c = s * SEG + l;
         if (c >= n) continue;
-        const int prow = poff[s] >= 0 ? (int)__builtin_rintf((float)poff[s] * __builtin_amdgcn_rcpf((float)n)) : -1;
+        const int prow = poff[s] >= 0 ? (int)__builtin_rintf((float)poff[s] * __builtin_amdgcn_rcpf((float)ldm)) : -1;
         if (prow >= 0 && prow < n) {
             sc.aux[prow] = c;
             sc.way[prow] = (short)c;
@@ -1037,7 +1050,7 @@ __device__ __forceinline__ void canonical_split_k(const SlotScratch<T, SEG, K>& 
         }
         lab[q] = okn ? -w[q] : (T)0;
         fx[q] = !okn;
-        base[q] = rowpass ? tc * n : tc;
+        base[q] = rowpass ? tc * ldm : tc;
     }
     for (int step = 0; step < n; ++step) {
         T m = fx[0] ? INF : lab[0];
@@ -1092,6 +1105,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
     using S = SegS<SEG>;
     using Bits = SegBits<SEG>;
     const T* __restrict__ M = sc.M;
+    const int ldm = sc.ld;   // row stride of M
     const int l = S::lane();
     const T INF = inf_of<T>();
     int c[K];
@@ -1103,14 +1117,14 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
 
     // ---- two-sided reduction and greedy start -------------------------------
     T v[K];
-    int poff[K];   // offset r * n of the row matched to each column, -1 when free
+    int poff[K];   // offset r * ld of the row matched to each column, -1 when free
     T ucol[K];     // dual of that row
     unsigned long long freem;
     {
         int rw[K];
         const unsigned long long taken = lap_reduce_start<T, SEG, K>(sc, n, c, ok, v, rw);
         for (int s = 0; s < K; ++s) {
-            poff[s] = rw[s] >= 0 ? __umul24(rw[s], n) : -1;
+            poff[s] = rw[s] >= 0 ? __umul24(rw[s], ldm) : -1;
             ucol[s] = rw[s] >= 0 ? (T)sc.vb[rw[s]] : (T)0;
         }
         freem = ~taken & (n >= 64 ? ~0ull : ((1ull << n) - 1ull));
@@ -1134,7 +1148,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
         way[s] = -1;
         used[s] = false;
     }
-    int i0n = row >= 0 ? __umul24(row, n) : 0;
+    int i0n = row >= 0 ? __umul24(row, ldm) : 0;
     T urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;
     T ui0 = urow0;
     T d0 = 0;
@@ -1199,7 +1213,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
                 for (int s = 0; s < K; ++s) {
                     if (!onpath[s]) continue;
                     const int wc = way[s] >= 0 ? way[s] : 0;
-                    newp[s] = way[s] >= 0 ? (int)sc.p[wc] : __umul24(row, n);
+                    newp[s] = way[s] >= 0 ? (int)sc.p[wc] : __umul24(row, ldm);
                     newu[s] = way[s] >= 0 ? (T)sc.u[wc] : urow0 + dmin;
                 }
             }
@@ -1218,7 +1232,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
                 }
                 row = freem ? __builtin_ctzll(freem) : -1;
                 freem &= freem - 1;
-                i0n = row >= 0 ? __umul24(row, n) : 0;
+                i0n = row >= 0 ? __umul24(row, ldm) : 0;
                 urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;
                 ui0 = urow0;
                 d0 = 0;
