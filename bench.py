@@ -39,9 +39,17 @@ HBM_PEAK_GBS = 8000.0
 # sources whose digest is recorded: any change to them makes the figure null
 # until the counters are taken again.
 TRAFFIC = {
-    # (step, N, dtype, complementary pairs once): (csrc digest, scaled FETCH bytes, scaled WRITE bytes)
-    (4, 25, "f64", True): ("8c74117988d43250", 493808.9 * 1024 * 2.0, 782546.7 * 1024 * 1.0),
-    (3, 25, "f64", True): ("8c74117988d43250", 397776.1 * 1024 * 2.0, 744000.8 * 1024 * 1.0),
+    # (step, N, precision, complementary pairs once): (csrc digest, scaled FETCH bytes, scaled WRITE bytes)
+    (4, 25, "fp64", True): ("f488a0d88be5ae48", 373938.0 * 1024 * 2.0, 780770.1 * 1024 * 1.0),
+    (3, 25, "fp64", True): ("f488a0d88be5ae48", 397330.4 * 1024 * 2.0, 744024.4 * 1024 * 1.0),
+    (4, 25, "fp32", True): ("f488a0d88be5ae48", 187191.3 * 1024 * 2.0, 389309.3 * 1024 * 1.0),
+    (3, 25, "fp32", True): ("f488a0d88be5ae48", 201915.5 * 1024 * 2.0, 372184.3 * 1024 * 1.0),
+    (4, 25, "fp32n", True): ("f488a0d88be5ae48", 187168.6 * 1024 * 2.0, 389861.8 * 1024 * 1.0),
+    (3, 25, "fp32n", True): ("f488a0d88be5ae48", 201887.5 * 1024 * 2.0, 372171.5 * 1024 * 1.0),
+    (4, 40, "fp64", True): ("f488a0d88be5ae48", 6878443.5 * 1024 * 2.0, 14736085.2 * 1024 * 1.0),
+    (3, 40, "fp64", True): ("f488a0d88be5ae48", 7952264.5 * 1024 * 2.0, 17059838.3 * 1024 * 1.0),
+    (4, 40, "fp32", True): ("f488a0d88be5ae48", 3441683.8 * 1024 * 2.0, 8011876.3 * 1024 * 1.0),
+    (3, 40, "fp32", True): ("f488a0d88be5ae48", 3716204.0 * 1024 * 2.0, 13669395.0 * 1024 * 1.0),
 }
 
 
@@ -341,7 +349,7 @@ def solver_leg(F, D, stream, state_iters=10, reps=3):
 
 def roofline(leg, step, digest):
     N, pair, elem, dur = leg["N"], leg["pair"], leg["elem"], leg["dur"]
-    rec = TRAFFIC.get((step, N, "f64" if elem == 8 else "f32", pair))
+    rec = TRAFFIC.get((step, N, leg["precision"], pair))
     ach = leg["bytes"][step] / (dur[step] * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": NAMES[step], "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS,
