@@ -688,10 +688,48 @@ __host__ __device__ inline size_t sweep_triple_lds(int N)
     return (run + (size_t)6 * N * N + (size_t)2 * kTripleJT * (N - 1) * (N - 2)) * sizeof(T);
 }
 
+// Position g of a location tile (g < kTripleJT (N-1)(N-2)): the tile-local
+// location jl and the compact (n', q'') of its row, which do not depend on the
+// tile, so a thread computes them once per size and keeps them in registers,
+// packed in one word (jl | n' << 8 | q'' << 16, each below 256).
+using TileSlot = unsigned;
+__device__ __forceinline__ TileSlot tile_slot(int g, int rowlen, int n2)
+{
+    const int jl = g / rowlen, r = g - jl * rowlen;
+    const int nc = r / n2;
+    return (unsigned)(jl & 255) | ((unsigned)nc << 8) | ((unsigned)(r - nc * n2) << 16);
+}
+
+// The six-way mean of the group at position g (slot sl) of the tile that
+// starts at location j0, in LDS: A and B rows of the tile, the C run and the
+// spread-share tables X.  Offsets are 24-bit products (all below 2^24).
+template <int PM, typename T>
+__device__ __forceinline__ void tile_group(T* __restrict__ As, T* __restrict__ Bs, T* __restrict__ Cs,
+                                           const T* __restrict__ X, int g, TileSlot sl, int j0, int N, int n1,
+                                           int n2, int rowlen, int NN)
+{
+    const int jl = (int)(sl & 255u), nc = (int)((sl >> 8) & 255u), qc = (int)(sl >> 16);
+    const int j = j0 + jl;
+    const int n = nc + (nc >= j);   // n' skips j
+    const int lo = min(j, n), hi = max(j, n);
+    int q = qc + (qc >= lo);        // q'' skips j and n
+    q += (q >= hi);
+    const int jq = q - (q > j);
+    T& a = As[g];
+    T& b = Bs[__umul24(jl, rowlen) + __umul24(jq, n2) + (n - (n > j) - (n > q))];
+    T& c = Cs[__umul24(__umul24(n, n1) + q - (q > n), n2) + (j - (j > n) - (j > q))];
+    const int jN = __umul24(j, N), nN = __umul24(n, N), qN = __umul24(q, N);
+    const T mean = six_way_mean<PM>(a, b, c, X[0 * NN + jN + n], X[1 * NN + jN + q], X[2 * NN + nN + j],
+                                    X[3 * NN + nN + q], X[4 * NN + qN + j], X[5 * NN + qN + n]);
+    a = mean;
+    b = mean;
+    c = mean;
+}
+
 // Workgroup b takes triple b - pre[s] of instance ids[s] (of instance s when
 // ids is null), s the last of the K prefix entries with pre[s] <= b.
 template <int PM, int NT>
-__global__ __launch_bounds__(NT) void k_sweep_triple(StoreT<PM>* __restrict__ Dd, const StoreT<PM>* __restrict__ CC,
+__global__ __launch_bounds__(NT, PM == kPrecF32Near ? 8 : 1) void k_sweep_triple(StoreT<PM>* __restrict__ Dd, const StoreT<PM>* __restrict__ CC,
                                                      StoreT<PM>* __restrict__ B, const int* __restrict__ tri,
                                                      const Inst* __restrict__ inst, const long long* __restrict__ pre,
                                                      const int* __restrict__ ids, int K, const int* __restrict__ act)
@@ -722,6 +760,10 @@ __global__ __launch_bounds__(NT) void k_sweep_triple(StoreT<PM>* __restrict__ Dd
     T* __restrict__ gC = Dk + (pair_index(N, k, p) * n2 + i) * NL * n2;
     const int tid = threadIdx.x;
     const int ntiles = (N + kTripleJT - 1) / kTripleJT;
+    // The decoded position of group tid stays in a register across the tiles
+    // (except in the certified mode with 1024 threads, below).
+    constexpr bool kDecodeInPlace = PM == kPrecF32Down && NT == kTripleThreads;
+    const TileSlot slot0 = kDecodeInPlace ? 0u : tile_slot(tid, rowlen, n2);
 
     // Requests: the C run, the tables (table m holds the spread shares of the
     // facility pair (f1, f2) below; diagonal entries are never read and load
@@ -789,24 +831,38 @@ __global__ __launch_bounds__(NT) void k_sweep_triple(StoreT<PM>* __restrict__ Dd
         }
         __syncthreads();
         fetch(ra, rb, tix + 2);
-        for (int g = tid; g < len; g += NT) {
-            const int jl = g / rowlen, r = g - jl * rowlen;
-            const int j = j0 + jl;
-            const int nc = r / n2, qc = r - nc * n2;   // n' (skipping j), q'' (skipping j and n)
-            const int n = nc + (nc >= j);
-            const int lo = min(j, n), hi = max(j, n);
-            int q = qc + (qc >= lo);
-            q += (q >= hi);
-            const int jq = q - (q > j);
-            T& a = As[jl * rowlen + r];
-            T& b = Bs[jl * rowlen + jq * n2 + (n - (n > j) - (n > q))];
-            T& c = Cs[(n * n1 + q - (q > n)) * n2 + (j - (j > n) - (j > q))];
-            const T mean = six_way_mean<PM>(a, b, c, X[0 * NN + j * N + n], X[1 * NN + j * N + q],
-                                           X[2 * NN + n * N + j], X[3 * NN + n * N + q],
-                                           X[4 * NN + q * N + j], X[5 * NN + q * N + n]);
-            a = mean;
-            b = mean;
-            c = mean;
+        if constexpr (kDecodeInPlace) {
+            // The certified six-way mean needs the registers that a kept slot
+            // and the 24-bit offsets take, to stay within the 64 VGPRs of two
+            // 1024-thread workgroups per CU (N = 25): each group is decoded in
+            // place.  The 512-thread variant keeps the slot: the VALU work it
+            // saves outweighs the workgroup per CU its registers cost there.
+            for (int g = tid; g < len; g += NT) {
+                const int jl = g / rowlen, r = g - jl * rowlen;
+                const int j = j0 + jl;
+                const int nc = r / n2, qc = r - nc * n2;   // n' (skipping j), q'' (skipping j and n)
+                const int n = nc + (nc >= j);
+                const int lo = min(j, n), hi = max(j, n);
+                int q = qc + (qc >= lo);
+                q += (q >= hi);
+                const int jq = q - (q > j);
+                T& a = As[jl * rowlen + r];
+                T& b = Bs[jl * rowlen + jq * n2 + (n - (n > j) - (n > q))];
+                T& c = Cs[(n * n1 + q - (q > n)) * n2 + (j - (j > n) - (j > q))];
+                const T mean = six_way_mean<PM>(a, b, c, X[0 * NN + j * N + n], X[1 * NN + j * N + q],
+                                               X[2 * NN + n * N + j], X[3 * NN + n * N + q],
+                                               X[4 * NN + q * N + j], X[5 * NN + q * N + n]);
+                a = mean;
+                b = mean;
+                c = mean;
+            }
+        } else {
+            // A tile has at most 2 NT groups (sweep_triple_lds): every thread
+            // takes position tid, whose slot it keeps, and the first len - NT
+            // threads (at most two waves) also position tid + NT, decoded here.
+            if (tid < len) tile_group<PM>(As, Bs, Cs, X, tid, slot0, j0, N, n1, n2, rowlen, NN);
+            if (tid + NT < len)
+                tile_group<PM>(As, Bs, Cs, X, tid + NT, tile_slot(tid + NT, rowlen, n2), j0, N, n1, n2, rowlen, NN);
         }
         __syncthreads();
 #pragma unroll
@@ -960,6 +1016,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(StoreT<PM>* _
     for (;;) {
         const int N = cur.N, n1 = cur.n1, n2 = cur.n2, NN = cur.NN, rowlen = cur.rowlen, ntiles = cur.ntiles;
         const int run = cur.run;
+        const TileSlot slot0 = tile_slot(tid, rowlen, n2);
         T* const gA = cur.gA;
         T* const gB = cur.gB;
         T* const gC = cur.gC;
@@ -1002,25 +1059,10 @@ __global__ __launch_bounds__(kTripleThreads) void k_sweep_triple_p(StoreT<PM>* _
             const bool on = t2 < ntiles;
             fetch(ra, rb, on ? gA : hA, on ? gB : hB, on ? N : hN, on ? rowlen : hrow,
                   on ? t2 * kTripleJT : min((t2 - ntiles) * kTripleJT, hlast));
-            for (int g = tid; live && g < len; g += kTripleThreads) {
-                const int jl = g / rowlen, r = g - jl * rowlen;
-                const int j = j0 + jl;
-                const int nc = r / n2, qc = r - nc * n2;   // n' (skipping j), q'' (skipping j and n)
-                const int n = nc + (nc >= j);
-                const int lo = min(j, n), hi = max(j, n);
-                int q = qc + (qc >= lo);
-                q += (q >= hi);
-                const int jq = q - (q > j);
-                T& a = As[jl * rowlen + r];
-                T& b = Bs[jl * rowlen + jq * n2 + (n - (n > j) - (n > q))];
-                T& c = Cs[(n * n1 + q - (q > n)) * n2 + (j - (j > n) - (j > q))];
-                const T mean = six_way_mean<PM>(a, b, c, X[0 * NN + j * N + n], X[1 * NN + j * N + q],
-                                               X[2 * NN + n * N + j], X[3 * NN + n * N + q],
-                                               X[4 * NN + q * N + j], X[5 * NN + q * N + n]);
-                a = mean;
-                b = mean;
-                c = mean;
-            }
+            if (live && tid < len) tile_group<PM>(As, Bs, Cs, X, tid, slot0, j0, N, n1, n2, rowlen, NN);
+            if (live && tid + kTripleThreads < len)
+                tile_group<PM>(As, Bs, Cs, X, tid + kTripleThreads, tile_slot(tid + kTripleThreads, rowlen, n2), j0,
+                               N, n1, n2, rowlen, NN);
             __syncthreads();
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
