@@ -727,12 +727,15 @@ __device__ __forceinline__ void tile_group(T* __restrict__ As, T* __restrict__ B
 }
 
 // Workgroup b takes triple b - pre[s] of instance ids[s] (of instance s when
-// ids is null), s the last of the K prefix entries with pre[s] <= b.
+// ids is null), s the last of the K prefix entries with pre[s] <= b.  The
+// round-to-nearest FP32 variant is compiled for eight waves per SIMD (64
+// VGPRs, two 1024-thread workgroups per CU), which it fits without spilling;
+// the FP64 one would spill, and the certified one fits by itself.
 template <int PM, int NT>
-__global__ __launch_bounds__(NT, PM == kPrecF32Near ? 8 : 1) void k_sweep_triple(StoreT<PM>* __restrict__ Dd, const StoreT<PM>* __restrict__ CC,
-                                                     StoreT<PM>* __restrict__ B, const int* __restrict__ tri,
-                                                     const Inst* __restrict__ inst, const long long* __restrict__ pre,
-                                                     const int* __restrict__ ids, int K, const int* __restrict__ act)
+__global__ __launch_bounds__(NT, PM == kPrecF32Near ? 8 : 1) void k_sweep_triple(
+    StoreT<PM>* __restrict__ Dd, const StoreT<PM>* __restrict__ CC, StoreT<PM>* __restrict__ B,
+    const int* __restrict__ tri, const Inst* __restrict__ inst, const long long* __restrict__ pre,
+    const int* __restrict__ ids, int K, const int* __restrict__ act)
 {
     using T = StoreT<PM>;
     extern __shared__ __align__(16) unsigned char smem[];
