@@ -112,6 +112,11 @@ __device__ __forceinline__ float add_down_to_float(double a, double b) {
 // FP32 step below the directed result, for a fraction of the work of
 // rounding every step toward -inf, which is what happens when a term is
 // negative (a state loaded by the caller may hold such entries).
+// The path for terms of either sign is a call, kept out of line so that the
+// sweeps' registers are sized for the common path.
+__device__ __attribute__((noinline)) float mean6_down_signed(float d0, float x0, float d1, float x1, float d2,
+                                                            float x2, float d3, float x3, float d4, float x4,
+                                                            float d5, float x5);
 __device__ __forceinline__ float mean6_down(float d0, float x0, float d1, float x1, float d2, float x2, float d3,
                                             float x3, float d4, float x4, float d5, float x5)
 {
@@ -126,6 +131,12 @@ __device__ __forceinline__ float mean6_down(float d0, float x0, float d1, float 
         sum += (double)d5 + (double)x5;
         return to_float_down((sum * (1.0 / 6.0)) * (1.0 - 0x1p-48));
     }
+    return mean6_down_signed(d0, x0, d1, x1, d2, x2, d3, x3, d4, x4, d5, x5);
+}
+__device__ __attribute__((noinline)) float mean6_down_signed(float d0, float x0, float d1, float x1, float d2,
+                                                            float x2, float d3, float x3, float d4, float x4,
+                                                            float d5, float x5)
+{
     double sum = add_down((double)d0, (double)x0);
     sum = add_down(sum, (double)d1);
     sum = add_down(sum, (double)x1);
@@ -728,11 +739,10 @@ __device__ __forceinline__ void tile_group(T* __restrict__ As, T* __restrict__ B
 
 // Workgroup b takes triple b - pre[s] of instance ids[s] (of instance s when
 // ids is null), s the last of the K prefix entries with pre[s] <= b.  The
-// round-to-nearest FP32 variant is compiled for eight waves per SIMD (64
-// VGPRs, two 1024-thread workgroups per CU), which it fits without spilling;
-// the FP64 one would spill, and the certified one fits by itself.
+// FP32 variants are compiled for eight waves per SIMD (64 VGPRs, two
+// 1024-thread workgroups per CU); the FP64 one would spill there.
 template <int PM, int NT>
-__global__ __launch_bounds__(NT, PM == kPrecF32Near ? 8 : 1) void k_sweep_triple(
+__global__ __launch_bounds__(NT, PM == kPrecF64 ? 1 : 8) void k_sweep_triple(
     StoreT<PM>* __restrict__ Dd, const StoreT<PM>* __restrict__ CC, StoreT<PM>* __restrict__ B,
     const int* __restrict__ tri, const Inst* __restrict__ inst, const long long* __restrict__ pre,
     const int* __restrict__ ids, int K, const int* __restrict__ act)
@@ -763,10 +773,8 @@ __global__ __launch_bounds__(NT, PM == kPrecF32Near ? 8 : 1) void k_sweep_triple
     T* __restrict__ gC = Dk + (pair_index(N, k, p) * n2 + i) * NL * n2;
     const int tid = threadIdx.x;
     const int ntiles = (N + kTripleJT - 1) / kTripleJT;
-    // The decoded position of group tid stays in a register across the tiles
-    // (except in the certified mode with 1024 threads, below).
-    constexpr bool kDecodeInPlace = PM == kPrecF32Down && NT == kTripleThreads;
-    const TileSlot slot0 = kDecodeInPlace ? 0u : tile_slot(tid, rowlen, n2);
+    // The decoded position of group tid stays in a register across the tiles.
+    const TileSlot slot0 = tile_slot(tid, rowlen, n2);
 
     // Requests: the C run, the tables (table m holds the spread shares of the
     // facility pair (f1, f2) below; diagonal entries are never read and load
@@ -834,39 +842,12 @@ __global__ __launch_bounds__(NT, PM == kPrecF32Near ? 8 : 1) void k_sweep_triple
         }
         __syncthreads();
         fetch(ra, rb, tix + 2);
-        if constexpr (kDecodeInPlace) {
-            // The certified six-way mean needs the registers that a kept slot
-            // and the 24-bit offsets take, to stay within the 64 VGPRs of two
-            // 1024-thread workgroups per CU (N = 25): each group is decoded in
-            // place.  The 512-thread variant keeps the slot: the VALU work it
-            // saves outweighs the workgroup per CU its registers cost there.
-            for (int g = tid; g < len; g += NT) {
-                const int jl = g / rowlen, r = g - jl * rowlen;
-                const int j = j0 + jl;
-                const int nc = r / n2, qc = r - nc * n2;   // n' (skipping j), q'' (skipping j and n)
-                const int n = nc + (nc >= j);
-                const int lo = min(j, n), hi = max(j, n);
-                int q = qc + (qc >= lo);
-                q += (q >= hi);
-                const int jq = q - (q > j);
-                T& a = As[jl * rowlen + r];
-                T& b = Bs[jl * rowlen + jq * n2 + (n - (n > j) - (n > q))];
-                T& c = Cs[(n * n1 + q - (q > n)) * n2 + (j - (j > n) - (j > q))];
-                const T mean = six_way_mean<PM>(a, b, c, X[0 * NN + j * N + n], X[1 * NN + j * N + q],
-                                               X[2 * NN + n * N + j], X[3 * NN + n * N + q],
-                                               X[4 * NN + q * N + j], X[5 * NN + q * N + n]);
-                a = mean;
-                b = mean;
-                c = mean;
-            }
-        } else {
-            // A tile has at most 2 NT groups (sweep_triple_lds): every thread
-            // takes position tid, whose slot it keeps, and the first len - NT
-            // threads (at most two waves) also position tid + NT, decoded here.
-            if (tid < len) tile_group<PM>(As, Bs, Cs, X, tid, slot0, j0, N, n1, n2, rowlen, NN);
-            if (tid + NT < len)
-                tile_group<PM>(As, Bs, Cs, X, tid + NT, tile_slot(tid + NT, rowlen, n2), j0, N, n1, n2, rowlen, NN);
-        }
+        // A tile has at most 2 NT groups (sweep_triple_lds): every thread
+        // takes position tid, whose slot it keeps, and the first len - NT
+        // threads (at most two waves) also position tid + NT, decoded here.
+        if (tid < len) tile_group<PM>(As, Bs, Cs, X, tid, slot0, j0, N, n1, n2, rowlen, NN);
+        if (tid + NT < len)
+            tile_group<PM>(As, Bs, Cs, X, tid + NT, tile_slot(tid + NT, rowlen, n2), j0, N, n1, n2, rowlen, NN);
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < 2; ++u) {

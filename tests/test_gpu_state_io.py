@@ -93,6 +93,92 @@ def test_certify_with_negative_entries(precision, complementary):
     g.close()
 
 
+@pytest.mark.parametrize("complementary", [True, False])
+def test_certified_sweep_rounds_down_with_negative_entries(complementary):
+    """Steps 1-3 in certified FP32 on a loaded state holding negative entries
+    (the six-way means then take the directed path for terms of either sign):
+    every member of every six-way group must end at or below the exact mean
+    of (member + spread share of its block), computed here in rational
+    arithmetic from the stored floats, and within a few FP32 steps of it."""
+    from fractions import Fraction
+    F, D = qapgen.small(8, 5)
+    N, n1, n2 = 8, 7, 6
+    g = Rlt2(F, D, precision="fp32", complementary=complementary)
+    g.ascend(2)
+    lb, B, C, Dst = g.read_state()
+    rng = np.random.default_rng(12)
+    nblk = N * N * n1 * n1
+    I, J, K, Nn = layout.c_index_arrays(N)
+    pos = {(int(I[x]), int(J[x]), int(K[x]), int(Nn[x])): x for x in range(nblk)}
+    Dn = Dst.reshape(nblk, n2 * n2).copy()
+    for beta in rng.choice(nblk, 60, replace=False):
+        i, j, k, n = int(I[beta]), int(J[beta]), int(K[beta]), int(Nn[beta])
+        e = rng.integers(0, n2 * n2)
+        v = -float(rng.uniform(0.5, 40.0))
+        Dn[beta, e] = v
+        Dn[pos[(k, n, i, j)], e] = v     # the complementary block's same entry
+    Cn = C.copy()
+    Cn[rng.choice(C.size, 40, replace=False)] -= rng.uniform(5.0, 200.0, 40)
+    Bn = B.copy()
+    Bn[rng.choice(B.size, 6, replace=False)] -= rng.uniform(50.0, 500.0, 6)
+    g.load_state(0, lb, Bn, Cn, Dn.ravel())
+    _, B2, C2, D2 = g.read_state()        # the stored floats
+    g.step(3)
+    _, B3, C3, D3 = g.read_state()
+    g.close()
+    assert not B3.any() and not C3.any()  # both spread onward and cleared
+    D2 = D2.reshape(nblk, n2 * n2)
+    D3 = D3.reshape(nblk, n2 * n2)
+    assert (D2 < 0).any()
+
+    def beta_of(a, la, b, lb_):
+        return ((a * N + la) * n1 + (b - (b > a))) * n1 + (lb_ - (lb_ > la))
+
+    def entry(a, la, b, lb_, c, lc):
+        return (c - (c > a) - (c > b)) * n2 + (lc - (lc > la) - (lc > lb_))
+
+    share = {}
+    def share_of(bt):
+        if bt not in share:
+            i, j = int(I[bt]), int(J[bt])
+            share[bt] = (Fraction(float(C2[bt])) + Fraction(float(B2[i * N + j])) / n1) / n2
+        return share[bt]
+
+    checked = signed = 0
+    worst = 0.0
+    for f0 in range(N):
+        for f1 in range(f0 + 1, N):
+            for f2 in range(f1 + 1, N):
+                for l0 in range(N):
+                    for l1 in range(N):
+                        if l1 == l0:
+                            continue
+                        for l2 in range(N):
+                            if l2 == l0 or l2 == l1:
+                                continue
+                            P = ((f0, l0), (f1, l1), (f2, l2))
+                            members = []
+                            for a, b, c in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+                                bt = beta_of(P[a][0], P[a][1], P[b][0], P[b][1])
+                                e = entry(P[a][0], P[a][1], P[b][0], P[b][1], P[c][0], P[c][1])
+                                members.append((bt, e))
+                            terms = [Fraction(float(D2[bt, e])) + share_of(bt) for bt, e in members]
+                            mean = sum(terms) / 6
+                            got = {float(D3[bt, e]) for bt, e in members}
+                            assert len(got) == 1, "members of one group differ"
+                            v = got.pop()
+                            assert Fraction(v) <= mean, (P, v, float(mean))
+                            scale = max(abs(float(t)) for t in terms) + abs(float(mean))
+                            gap = float(mean - Fraction(v))
+                            assert gap <= 4 * 2.0 ** -23 * scale, (P, v, float(mean), gap)
+                            worst = max(worst, gap / scale if scale else 0.0)
+                            checked += 1
+                            signed += any(float(D2[bt, e]) < 0 or share_of(bt) < 0 for bt, e in members)
+    print(f"certified sweep: {checked} groups, {signed} with a negative term, worst gap {worst:.2e} of the scale",
+          flush=True)
+    assert signed > 0
+
+
 def test_load_state_rejects_bad_input():
     F, D = qapgen.small(8, 0)
     g = Rlt2(F, D)
