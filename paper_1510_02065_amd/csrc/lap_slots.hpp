@@ -157,8 +157,14 @@ struct SlotScratch {
     int* aux;    // row ownership, then sigma (column of row r)
     short* p;    // row matched to column c (or -1); the flat solver keeps r*ld
     short* way;  // predecessor column on the shortest path
-    double* u;   // dual of the row matched to column c; scratch in the completion
-    double* vb;  // column duals in the canonical passes; scratch in the completion
+    double* u;   // n doubles: the FP64 scratch of the certified completion and the auction
+    double* vb;  // n doubles after u, likewise
+    // The same two arrays as values of type T, used by every other phase (for
+    // FP32, their first halves): ut[c] = dual of the row matched to column c,
+    // vt = row minima in the start, then column duals in the canonical passes.
+    // A phase reads an array only through the view it was written through.
+    T* ut;
+    T* vt;
     __device__ SlotScratch(unsigned char* base, int n) {
         const size_t mb = SlotLds<T, SEG, K>::mat_bytes(n);
         M = reinterpret_cast<T*>(base);
@@ -168,6 +174,8 @@ struct SlotScratch {
         way = p + n;
         u = reinterpret_cast<double*>(base + mb + SlotLds<T, SEG, K>::idx_bytes(n));
         vb = u + n;
+        ut = reinterpret_cast<T*>(u);
+        vt = reinterpret_cast<T*>(vb);
     }
 };
 
@@ -179,7 +187,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
 // Canonical dual and residual, from the solver's optimal duals and matching:
 // v (column duals) and p (row matched to each column) of this lane's K
 // columns, ucol the dual of that row; the LDS copies sc.p (row indices) and
-// sc.u (row dual per column) hold the same for every column.
+// sc.ut (row dual per column) hold the same for every column.
 template <typename T, int SEG, int K, bool DOWN>
 __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG, K>& sc, int n,
                                                        T* __restrict__ R, long long ldr, T* __restrict__ duals,
@@ -221,7 +229,7 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
             const int cc = S::imin(lm == dmin ? lc : NONE);
             if (cc >= n) break;
             const int r = sc.p[cc];
-            const T ur = (T)sc.u[cc];
+            const T ur = sc.ut[cc];
             for (int s = 0; s < K; ++s) {
                 done[s] = done[s] || (c[s] == cc);
                 const T nd = dmin + ((M[r * ldm + (ok[s] ? c[s] : 0)] - ur) - v[s]);
@@ -232,19 +240,19 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
             if (!ok[s]) x[s] = 0;
     }
 
-    // sigma (column of row r) in sc.aux, v in sc.vb; the solver's row dual
+    // sigma (column of row r) in sc.aux, v in sc.vt; the solver's row dual
     // u_r is the dual stored at column sigma(r).
     wave_sync();
     for (int s = 0; s < K; ++s) {
         if (ok[s] && p[s] >= 0) sc.aux[p[s]] = c[s];
-        if (ok[s]) sc.vb[c[s]] = (double)v[s];
+        if (ok[s]) sc.vt[c[s]] = v[s];
     }
     wave_sync();
     int sg[K];     // lane as rows: sigma of this lane's rows
     T urow[K];
     for (int s = 0; s < K; ++s) {
         sg[s] = ok[s] ? sc.aux[c[s]] : 0;
-        urow[s] = (T)sc.u[sg[s]];
+        urow[s] = sc.ut[sg[s]];
     }
 
     // ---- row-canonical point (lanes = rows) ---------------------------------
@@ -269,7 +277,7 @@ __device__ __forceinline__ double lap_canonical_finish(const SlotScratch<T, SEG,
             const int rr = S::imin(lm == dmin ? lc : NONE);
             if (rr >= n) break;
             const int cs = sc.aux[rr];
-            const T vcs = (T)sc.vb[cs];
+            const T vcs = sc.vt[cs];
             for (int s = 0; s < K; ++s) {
                 done[s] = done[s] || (c[s] == rr);
                 const T nd = dmin + ((M[(ok[s] ? c[s] : 0) * ldm + cs] - vcs) - urow[s]);
@@ -317,8 +325,8 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
         // two points ----
         for (int s = 0; s < K; ++s) {
             if (!ok[s]) continue;
-            sc.u[c[s]] = vc[s];
-            sc.vb[c[s]] = ur[s];
+            sc.ut[c[s]] = vc[s];
+            sc.vt[c[s]] = ur[s];
         }
         wave_sync();
         T uc[K], vr[K];   // uc: lane as rows; vr: lane as columns
@@ -326,13 +334,13 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             uc[s] = INF;
             vr[s] = INF;
             if (ok[s]) {
-                for (int q = 0; q < n; ++q) uc[s] = tmin(uc[s], M[c[s] * ldm + q] - (T)sc.u[q]);
-                for (int r = 0; r < n; ++r) vr[s] = tmin(vr[s], M[r * ldm + c[s]] - (T)sc.vb[r]);
+                for (int q = 0; q < n; ++q) uc[s] = tmin(uc[s], M[c[s] * ldm + q] - sc.ut[q]);
+                for (int r = 0; r < n; ++r) vr[s] = tmin(vr[s], M[r * ldm + c[s]] - sc.vt[r]);
             }
         }
         wave_sync();
         for (int s = 0; s < K; ++s)
-            if (ok[s]) sc.u[c[s]] = uc[s];
+            if (ok[s]) sc.ut[c[s]] = uc[s];
         wave_sync();
         if (R != nullptr) {
             for (int s = 0; s < K; ++s) {
@@ -340,8 +348,8 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
                 T* Rr = R + c[s];
                 for (int r = 0; r < n; ++r, Rr += ldr) {
                     const T m = M[r * ldm + c[s]];
-                    const T r1 = (m - vc[s]) - (T)sc.u[r];
-                    const T r2 = (m - (T)sc.vb[r]) - vr[s];
+                    const T r1 = (m - vc[s]) - sc.ut[r];
+                    const T r2 = (m - sc.vt[r]) - vr[s];
                     *Rr = (T)0.5 * (r1 + r2);
                 }
             }
@@ -416,12 +424,15 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
             for (int s = 0; s < K; ++s) {
                 if (!ok[s]) continue;
                 T* Rr = R + c[s];
+                const double aV = __builtin_fabs(V[s]) * 0x1p-50;
                 for (int r = 0; r < n; ++r, Rr += ldr) {
                     const double m = (double)M[r * ldm + c[s]];
                     const double ur_ = sc.u[r];
                     const double t = (m - V[s]) - ur_;
-                    const double margin = ((__builtin_fabs(m) + __builtin_fabs(V[s])) + __builtin_fabs(ur_)) * 0x1p-50;
-                    *Rr = to_float_down(__builtin_fmax(t - margin, 0.0));
+                    // 2^-50 (|M| + |U| + |V|), the sum rounded once before
+                    // the FMA and once in it: >= (1 - 2^-52) of the exact one.
+                    const double margin = __builtin_fma(__builtin_fabs(m) + __builtin_fabs(ur_), 0x1p-50, aV);
+                    *Rr = to_float_down_nonneg(__builtin_fmax(t - margin, 0.0));
                 }
             }
         }
@@ -461,7 +472,7 @@ __device__ __forceinline__ double lap_complete(const SlotScratch<T, SEG, K>& sc,
 // M_rc - u_r = v_c.  On the structured blocks of the dual ascent this leaves
 // far fewer rows free than a column reduction alone, and every free row costs
 // Dijkstra steps.  Lane layout as in lap_concentrate_slots (c[s] = this
-// lane's columns, which are also its rows).  On return sc.vb[r] = u_r for every
+// lane's columns, which are also its rows).  On return sc.vt[r] = u_r for every
 // row r < n, kept through the Hungarian phase (a free row enters with that
 // dual); v[s] and row[s] (matched row or -1) for each of the lane's columns;
 // the result is the mask of matched rows (bit r).  sc.u is used as scratch.
@@ -473,9 +484,11 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
     // Each loop reads kReduceChunk LDS entries before it uses any of them
     // (indices past n - 1 re-read entry n - 1, which changes no minimum and
     // sets no new bit), so a lane waits for LDS once per chunk.  Zero masks are
-    // 32-bit when a problem has at most 32 columns.  The minima are kept with
-    // selects rather than branches (the first of equal values stays), and row
-    // offsets are 24-bit products (n <= 64).
+    // 32-bit when a problem has at most 32 columns.  The minima are fmin (one
+    // instruction in FP64 where a select takes three; equal values can differ
+    // only in the sign of a zero, which no later comparison or sum sees), the
+    // zero masks selects rather than branches, and row offsets are 24-bit
+    // products (n <= 64).
     constexpr int kReduceChunk = 8;
     using Mask = std::conditional_t<(SEG * K <= 32), unsigned, unsigned long long>;
     const T* __restrict__ M = sc.M;
@@ -489,9 +502,9 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
 #pragma unroll
             for (int e = 0; e < kReduceChunk; ++e) m[e] = Mr[min(q0 + e, n - 1)];
 #pragma unroll
-            for (int e = 0; e < kReduceChunk; ++e) um = m[e] < um ? m[e] : um;
+            for (int e = 0; e < kReduceChunk; ++e) um = tmin(m[e], um);
         }
-        sc.vb[c[s]] = (double)um;
+        sc.vt[c[s]] = um;
     }
     wave_sync();
     Mask zc[K];   // zero mask of each of this lane's columns
@@ -501,21 +514,21 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
         zc[s] = 0;
         if (!ok[s]) continue;
         const T* __restrict__ Mc = M + c[s];
-        T vm = Mc[0] - (T)sc.vb[0];
+        T vm = Mc[0] - sc.vt[0];
         Mask z = 1;
         for (int r0 = 0; r0 < n; r0 += kReduceChunk) {
             T x[kReduceChunk];
 #pragma unroll
             for (int e = 0; e < kReduceChunk; ++e) {
                 const int r = min(r0 + e, n - 1);
-                x[e] = Mc[__umul24(r, ldm)] - (T)sc.vb[r];
+                x[e] = Mc[__umul24(r, ldm)] - sc.vt[r];
             }
 #pragma unroll
             for (int e = 0; e < kReduceChunk; ++e) {
                 const Mask bit = Mask(1) << min(r0 + e, n - 1);
                 const bool lt = x[e] < vm, eq = x[e] == vm;
                 z = lt ? bit : (eq ? (z | bit) : z);
-                vm = lt ? x[e] : vm;
+                vm = tmin(x[e], vm);
             }
         }
         v[s] = vm;
@@ -627,10 +640,10 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
     T ucol[K];     // dual of that row
     const unsigned long long taken = lap_reduce_start<T, SEG, K>(sc, n, c, ok, v, p);
     for (int s = 0; s < K; ++s) {
-        ucol[s] = p[s] >= 0 ? (T)sc.vb[p[s]] : (T)0;
+        ucol[s] = p[s] >= 0 ? sc.vt[p[s]] : (T)0;
         if (!ok[s]) continue;
         sc.p[c[s]] = p[s];
-        sc.u[c[s]] = (double)ucol[s];
+        sc.ut[c[s]] = ucol[s];
         sc.aux[c[s]] = ((taken >> c[s]) & 1ull) ? 0 : NONE;   // lane as row c[s]
     }
     wave_sync();
@@ -647,7 +660,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
             used[s] = false;
         }
         int i0 = i;     // row being scanned
-        const T ufree = (T)sc.vb[i];   // dual of the free row (its row minimum)
+        const T ufree = sc.vt[i];   // dual of the free row (its row minimum)
         T ui0 = ufree;  // dual of the row being scanned
         T d0 = 0;       // distance at which row i0 was reached
         int j0 = -1;    // column through which row i0 was reached
@@ -680,7 +693,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
             for (int s = 0; s < K; ++s) used[s] = used[s] || (c[s] == j1);
             j0 = j1;
             i0 = pj;
-            ui0 = (T)sc.u[j1c];
+            ui0 = sc.ut[j1c];
             d0 = dmin;
         }
         // Dual shift of the scanned tree; predecessors published for the flip.
@@ -692,7 +705,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
             }
             if (!ok[s]) continue;
             sc.way[c[s]] = way[s];
-            sc.u[c[s]] = (double)ucol[s];
+            sc.ut[c[s]] = ucol[s];
         }
         wave_sync();
         // Flip the path: every column on it takes the row (and row dual) of
@@ -710,7 +723,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
             const int w = sc.way[j];
             const int wc = w >= 0 ? w : 0;
             const int pw = sc.p[wc];
-            const T uw = (T)sc.u[wc];
+            const T uw = sc.ut[wc];
             for (int s = 0; s < K; ++s) {
                 if (c[s] == j) {
                     newp[s] = w >= 0 ? pw : i;
@@ -725,7 +738,7 @@ __device__ __forceinline__ double lap_concentrate_slots(const SlotScratch<T, SEG
             ucol[s] = newu[s];
             if (!ok[s]) continue;
             sc.p[c[s]] = p[s];
-            sc.u[c[s]] = (double)ucol[s];
+            sc.ut[c[s]] = ucol[s];
         }
         wave_sync();
     }
@@ -762,7 +775,7 @@ struct SegBits {
 // their lowest candidate index.  On return (lane as column / as row, K = 1
 // layout) vc is the column-canonical dual of the lane's column, ur the
 // row-canonical dual of its row and sg its row's column.  Expects sc.p
-// (offset r*ld of the row matched to each column) and sc.u (that row's dual);
+// (offset r*ld of the row matched to each column) and sc.ut (that row's dual);
 // poff is this lane's.
 template <typename T, int SEG>
 __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc, int n, T v, int poff, T& vc,
@@ -786,7 +799,7 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
         sc.aux[prow] = l;
         sc.way[prow] = (short)l;
     }
-    if (l < n) sc.vb[l] = (double)v;
+    if (l < n) sc.vt[l] = v;
     wave_sync();
     const bool rowpass = l >= H;
     const short* __restrict__ keys = rowpass ? sc.way : sc.p;
@@ -801,9 +814,9 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
         if (rowpass) {
             int sgt = sc.aux[tc];
             sgt = (sgt >= 0 && sgt < n) ? sgt : 0;
-            w[q] = (T)sc.u[sgt];       // u_r of row t: the dual stored at its column
+            w[q] = sc.ut[sgt];       // u_r of row t: the dual stored at its column
         } else {
-            w[q] = (T)sc.vb[tc];       // v_q
+            w[q] = sc.vt[tc];       // v_q
         }
         lab[q] = okn ? -w[q] : (T)0;
         fx[q] = !okn;
@@ -819,7 +832,7 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
         const int f = HS::imin(cand);
         const int fc = f < n ? f : 0;
         const int key = keys[fc];
-        const T s1 = rowpass ? (T)sc.vb[key] : (T)sc.u[fc];
+        const T s1 = rowpass ? sc.vt[key] : sc.ut[fc];
         for (int q = 0; q < 2; ++q) {
             fx[q] = fx[q] || (t[q] == f);
             const T nd = dmin + ((M[base[q] + key] - s1) - w[q]);
@@ -832,15 +845,15 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
     for (int q = 0; q < 2; ++q) {
         if (t[q] < n) {
             if (rowpass)
-                sc.u[t[q]] = (double)(w[q] + lab[q]);
+                sc.ut[t[q]] = w[q] + lab[q];
             else
-                sc.vb[t[q]] = (double)(w[q] + lab[q]);
+                sc.vt[t[q]] = w[q] + lab[q];
         }
     }
     wave_sync();
     const int lc = l < n ? l : 0;
-    vc = (T)sc.vb[lc];
-    ur = (T)sc.u[lc];
+    vc = sc.vt[lc];
+    ur = sc.ut[lc];
     sg = sc.aux[lc];
     wave_sync();
 }
@@ -881,10 +894,10 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
         const unsigned long long taken = lap_reduce_start<T, SEG, 1>(sc, n, cl, okl, va, rw);
         v = va[0];
         poff = rw[0] >= 0 ? __umul24(rw[0], ldm) : -1;
-        ucol = rw[0] >= 0 ? (T)sc.vb[rw[0]] : (T)0;
+        ucol = rw[0] >= 0 ? sc.vt[rw[0]] : (T)0;
         if (ok) {
             sc.p[l] = poff;
-            sc.u[l] = (double)ucol;
+            sc.ut[l] = ucol;
         }
         freem = ~taken & (n >= 64 ? ~0ull : ((1ull << n) - 1ull));
     }
@@ -897,7 +910,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
     int way = -1;
     bool used = false;
     int i0n = row >= 0 ? __umul24(row, ldm) : 0;   // offset of the row being scanned
-    T urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;   // dual of the free row being inserted
+    T urow0 = row >= 0 ? sc.vt[row] : (T)0;   // dual of the free row being inserted
     T ui0 = urow0;                                // dual of the row being scanned
     T d0 = 0;
     int j0 = -1;
@@ -913,7 +926,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
         const int j1 = Bits::first(Bits::get(live && lm == dmin));
         const int jc = j1 >= 0 ? j1 : 0;
         const int pj = sc.p[jc];
-        const T uj = (T)sc.u[jc];
+        const T uj = sc.ut[jc];
         const bool aug = active && (j1 < 0 || pj < 0);
         used = used || (l == j1);
         j0 = j1;
@@ -931,7 +944,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
                 }
                 if (ok) {
                     sc.way[l] = way;
-                    sc.u[l] = (double)ucol;
+                    sc.ut[l] = ucol;
                 }
             }
             wave_sync();
@@ -944,7 +957,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
             if (aug) {
                 const int wc = way >= 0 ? way : 0;
                 const int pw = sc.p[wc];
-                const T uw = (T)sc.u[wc];
+                const T uw = sc.ut[wc];
                 bool onpath = false;
                 for (int j = j1, hop = 0; j >= 0 && hop <= n; ++hop) {
                     onpath = onpath || (l == j);
@@ -961,7 +974,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
                 ucol = newu;
                 if (ok) {
                     sc.p[l] = poff;
-                    sc.u[l] = (double)ucol;
+                    sc.ut[l] = ucol;
                 }
                 row = Bits::first(freem);
                 freem &= freem - 1;
@@ -969,7 +982,7 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
                 way = -1;
                 used = false;
                 i0n = row >= 0 ? __umul24(row, ldm) : 0;
-                urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;
+                urow0 = row >= 0 ? sc.vt[row] : (T)0;
                 ui0 = urow0;
                 d0 = 0;
                 j0 = -1;
@@ -1028,7 +1041,7 @@ __device__ __forceinline__ void canonical_split_k(const SlotScratch<T, SEG, K>& 
             sc.aux[prow] = c;
             sc.way[prow] = (short)c;
         }
-        sc.vb[c] = (double)v[s];
+        sc.vt[c] = v[s];
     }
     wave_sync();
     const bool rowpass = l >= H;
@@ -1044,9 +1057,9 @@ __device__ __forceinline__ void canonical_split_k(const SlotScratch<T, SEG, K>& 
         if (rowpass) {
             int sgt = sc.aux[tc];
             sgt = (sgt >= 0 && sgt < n) ? sgt : 0;
-            w[q] = (T)sc.u[sgt];
+            w[q] = sc.ut[sgt];
         } else {
-            w[q] = (T)sc.vb[tc];
+            w[q] = sc.vt[tc];
         }
         lab[q] = okn ? -w[q] : (T)0;
         fx[q] = !okn;
@@ -1062,7 +1075,7 @@ __device__ __forceinline__ void canonical_split_k(const SlotScratch<T, SEG, K>& 
         const int f = HS::imin(cand);
         const int fc = f < n ? f : 0;
         const int key = keys[fc];
-        const T s1 = rowpass ? (T)sc.vb[key] : (T)sc.u[fc];
+        const T s1 = rowpass ? sc.vt[key] : sc.ut[fc];
         for (int q = 0; q < NQ; ++q) {
             fx[q] = fx[q] || (t[q] == f);
             const T nd = dmin + ((M[base[q] + key] - s1) - w[q]);
@@ -1073,17 +1086,17 @@ __device__ __forceinline__ void canonical_split_k(const SlotScratch<T, SEG, K>& 
     for (int q = 0; q < NQ; ++q) {
         if (t[q] < n) {
             if (rowpass)
-                sc.u[t[q]] = (double)(w[q] + lab[q]);
+                sc.ut[t[q]] = w[q] + lab[q];
             else
-                sc.vb[t[q]] = (double)(w[q] + lab[q]);
+                sc.vt[t[q]] = w[q] + lab[q];
         }
     }
     wave_sync();
     for (int s = 0; s < K; ++s) {
         const int c = s * SEG + l;
         const int cc = c < n ? c : 0;
-        vc[s] = (T)sc.vb[cc];
-        ur[s] = (T)sc.u[cc];
+        vc[s] = sc.vt[cc];
+        ur[s] = sc.ut[cc];
         sg[s] = sc.aux[cc];
     }
     wave_sync();
@@ -1125,7 +1138,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
         const unsigned long long taken = lap_reduce_start<T, SEG, K>(sc, n, c, ok, v, rw);
         for (int s = 0; s < K; ++s) {
             poff[s] = rw[s] >= 0 ? __umul24(rw[s], ldm) : -1;
-            ucol[s] = rw[s] >= 0 ? (T)sc.vb[rw[s]] : (T)0;
+            ucol[s] = rw[s] >= 0 ? sc.vt[rw[s]] : (T)0;
         }
         freem = ~taken & (n >= 64 ? ~0ull : ((1ull << n) - 1ull));
     }
@@ -1133,7 +1146,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
     for (int s = 0; s < K; ++s) {
         if (!ok[s]) continue;
         sc.p[c[s]] = poff[s];
-        sc.u[c[s]] = (double)ucol[s];
+        sc.ut[c[s]] = ucol[s];
     }
     wave_sync();
 
@@ -1149,7 +1162,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
         used[s] = false;
     }
     int i0n = row >= 0 ? __umul24(row, ldm) : 0;
-    T urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;
+    T urow0 = row >= 0 ? sc.vt[row] : (T)0;
     T ui0 = urow0;
     T d0 = 0;
     int j0 = -1;
@@ -1175,7 +1188,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
         }
         const int jc = j1 >= 0 ? j1 : 0;
         const int pj = sc.p[jc];
-        const T uj = (T)sc.u[jc];
+        const T uj = sc.ut[jc];
         const bool aug = active && (j1 < 0 || pj < 0);
         for (int s = 0; s < K; ++s) used[s] = used[s] || (c[s] == j1);
         j0 = j1;
@@ -1192,7 +1205,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
                     }
                     if (ok[s]) {
                         sc.way[c[s]] = way[s];
-                        sc.u[c[s]] = (double)ucol[s];
+                        sc.ut[c[s]] = ucol[s];
                     }
                 }
             }
@@ -1214,7 +1227,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
                     if (!onpath[s]) continue;
                     const int wc = way[s] >= 0 ? way[s] : 0;
                     newp[s] = way[s] >= 0 ? (int)sc.p[wc] : __umul24(row, ldm);
-                    newu[s] = way[s] >= 0 ? (T)sc.u[wc] : urow0 + dmin;
+                    newu[s] = way[s] >= 0 ? sc.ut[wc] : urow0 + dmin;
                 }
             }
             wave_sync();
@@ -1224,7 +1237,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
                     ucol[s] = newu[s];
                     if (ok[s]) {
                         sc.p[c[s]] = poff[s];
-                        sc.u[c[s]] = (double)ucol[s];
+                        sc.ut[c[s]] = ucol[s];
                     }
                     dist[s] = INF;
                     way[s] = -1;
@@ -1233,7 +1246,7 @@ __device__ __forceinline__ double lap_concentrate_flatk(const SlotScratch<T, SEG
                 row = freem ? __builtin_ctzll(freem) : -1;
                 freem &= freem - 1;
                 i0n = row >= 0 ? __umul24(row, ldm) : 0;
-                urow0 = row >= 0 ? (T)sc.vb[row] : (T)0;
+                urow0 = row >= 0 ? sc.vt[row] : (T)0;
                 ui0 = urow0;
                 d0 = 0;
                 j0 = -1;

@@ -86,6 +86,12 @@ __device__ __forceinline__ float to_float_down(double x) {
     if ((double)f > x) f = next_down(f);
     return f;
 }
+// Largest float <= x, for x >= 0: a nearest float above x is then positive,
+// so the float below it is its bit pattern minus one.
+__device__ __forceinline__ float to_float_down_nonneg(double x) {
+    const float f = (float)x;
+    return (double)f > x ? __int_as_float(__float_as_int(f) - 1) : f;
+}
 __device__ __forceinline__ float mul_down_to_float(double a, double b) {
     const double p = a * b;
     const double err = __builtin_fma(a, b, -p);
@@ -129,7 +135,7 @@ __device__ __forceinline__ float mean6_down(float d0, float x0, float d1, float 
         sum += (double)d3 + (double)x3;
         sum += (double)d4 + (double)x4;
         sum += (double)d5 + (double)x5;
-        return to_float_down((sum * (1.0 / 6.0)) * (1.0 - 0x1p-48));
+        return to_float_down_nonneg((sum * (1.0 / 6.0)) * (1.0 - 0x1p-48));
     }
     return mean6_down_signed(d0, x0, d1, x1, d2, x2, d3, x3, d4, x4, d5, x5);
 }
