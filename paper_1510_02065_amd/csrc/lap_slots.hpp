@@ -757,6 +757,13 @@ struct SegBits {
         else
             return (b >> (threadIdx.x & (64 - SEG))) & ((1ull << SEG) - 1);
     }
+    // This lane's segment's bits of a wave mask.
+    __device__ __forceinline__ static unsigned long long seg(unsigned long long b) {
+        if constexpr (SEG == 64)
+            return b;
+        else
+            return (b >> (threadIdx.x & (64 - SEG))) & ((1ull << SEG) - 1);
+    }
     __device__ __forceinline__ static int first(unsigned long long bits) {
         if constexpr (SEG == 64)
             return bits ? __builtin_ctzll(bits) : -1;
@@ -806,7 +813,7 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
     const int h = l & (H - 1);
     int t[2], base[2];
     T lab[2], w[2];
-    bool fx[2];   // fixed (or absent) node
+    unsigned long long fxm[2];   // fixed (or absent) node, as wave masks
     for (int q = 0; q < 2; ++q) {
         t[q] = h + q * H;
         const bool okn = t[q] < n;
@@ -819,24 +826,33 @@ __device__ __forceinline__ void canonical_split(const SlotScratch<T, SEG, 1>& sc
             w[q] = sc.vt[tc];       // v_q
         }
         lab[q] = okn ? -w[q] : (T)0;
-        fx[q] = !okn;
+        fxm[q] = ballot64(!okn);
         // M entry of node t relaxed through a fixed node with key K (column
         // pass: K = offset of p(f); row pass: K = sigma(f)) is M[base + K].
         base[q] = rowpass ? tc * ldm : tc;
     }
-    // Branch-free steps: every node's relaxation is computed (the entry read
-    // for a fixed or absent node is in range and its result is discarded).
-    for (int step = 0; step < n; ++step) {
-        const T dmin = HS::min(tmin(fx[0] ? INF : lab[0], fx[1] ? INF : lab[1]));
-        const int cand = (!fx[0] && lab[0] == dmin) ? t[0] : ((!fx[1] && lab[1] == dmin) ? t[1] : NONE);
+    // Every segment takes the wave's largest n steps, so the loop counter is
+    // scalar: a segment past its own n has every node fixed, and its further
+    // steps (with key 0) change no label.  The steps are branch-free: every
+    // node's relaxation is computed (the entry read for a fixed or absent node
+    // is in range and its result is discarded).
+    int nw = 0;
+#pragma unroll
+    for (int g = 0; g < 64 / SEG; ++g) nw = ::max(nw, __builtin_amdgcn_readlane(n, g * SEG));
+    for (int step = 0; step < nw; ++step) {
+        const bool fx0 = lane_bit(fxm[0]), fx1 = lane_bit(fxm[1]);
+        const T dmin = HS::min(tmin(fx0 ? INF : lab[0], fx1 ? INF : lab[1]));
+        const int cand = (!fx0 && lab[0] == dmin) ? t[0] : ((!fx1 && lab[1] == dmin) ? t[1] : NONE);
         const int f = HS::imin(cand);
-        const int fc = f < n ? f : 0;
-        const int key = keys[fc];
+        const bool fin = f < n;
+        const int fc = fin ? f : 0;
+        const int kf = keys[fc];
+        const int key = fin ? kf : 0;
         const T s1 = rowpass ? sc.vt[key] : sc.ut[fc];
         for (int q = 0; q < 2; ++q) {
-            fx[q] = fx[q] || (t[q] == f);
+            fxm[q] |= ballot64(t[q] == f);
             const T nd = dmin + ((M[base[q] + key] - s1) - w[q]);
-            lab[q] = (!fx[q] && nd < lab[q]) ? nd : lab[q];
+            lab[q] = (!lane_bit(fxm[q]) && nd < lab[q]) ? nd : lab[q];
         }
     }
     wave_sync();
@@ -908,32 +924,41 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
     freem &= freem - 1;
     T dist = INF;
     int way = -1;
-    bool used = false;
     int i0n = row >= 0 ? __umul24(row, ldm) : 0;   // offset of the row being scanned
     T urow0 = row >= 0 ? sc.vt[row] : (T)0;   // dual of the free row being inserted
     T ui0 = urow0;                                // dual of the row being scanned
     T d0 = 0;
     int j0 = -1;
-    while (ballot64(row >= 0) != 0) {
-        const bool active = row >= 0;
-        const bool live = active && ok && !used;
+    // Lane predicates as wave masks: the columns in range, the columns
+    // already in their problem's shortest-path tree, the lanes of problems
+    // still inserting a row.
+    const unsigned long long okm = ballot64(ok);
+    unsigned long long usedm = 0;
+    for (;;) {
+        const unsigned long long actm = ballot64(row >= 0);
+        if (actm == 0) break;
+        const unsigned long long livem = actm & okm & ~usedm;
+        const bool live = lane_bit(livem);
         const T cur = d0 + ((M[i0n + (ok ? l : 0)] - ui0) - v);
         const bool better = live && cur < dist;
         dist = better ? cur : dist;
         way = better ? j0 : way;
         const T lm = live ? dist : INF;
         const T dmin = S::min(lm);
-        const int j1 = Bits::first(Bits::get(live && lm == dmin));
+        const int j1 = Bits::first(Bits::seg(ballot64(lm == dmin) & livem));
         const int jc = j1 >= 0 ? j1 : 0;
         const int pj = sc.p[jc];
         const T uj = sc.ut[jc];
-        const bool aug = active && (j1 < 0 || pj < 0);
-        used = used || (l == j1);
+        // Problems whose step reached an unmatched column (or no column).
+        const unsigned long long augm = actm & (ballot64(j1 < 0) | ballot64(pj < 0));
+        usedm |= ballot64(l == j1);
         j0 = j1;
         i0n = pj >= 0 ? pj : 0;
         ui0 = uj;
         d0 = dmin;
-        if (ballot64(aug) != 0) {
+        if (augm != 0) {
+            const bool aug = lane_bit(augm);
+            const bool used = lane_bit(usedm);
             // Dual shift of the scanned tree (the reached column has dist =
             // dmin, so its shift is 0), predecessors published for the flip.
             if (aug) {
@@ -980,13 +1005,13 @@ __device__ __forceinline__ double lap_concentrate_flat(const SlotScratch<T, SEG,
                 freem &= freem - 1;
                 dist = INF;
                 way = -1;
-                used = false;
                 i0n = row >= 0 ? __umul24(row, ldm) : 0;
                 urow0 = row >= 0 ? sc.vt[row] : (T)0;
                 ui0 = urow0;
                 d0 = 0;
                 j0 = -1;
             }
+            usedm &= ~augm;   // the new rows start with empty trees
             wave_sync();
         }
     }

@@ -12,6 +12,10 @@ namespace qap {
 // Wave-wide ballot of a predicate; taking a bool (not an int as __ballot
 // does) lets the compiler use the comparison's lane mask directly.
 __device__ __forceinline__ unsigned long long ballot64(bool pred) { return __builtin_amdgcn_ballot_w64(pred); }
+// This lane's bit of a wave-uniform lane mask.  A predicate kept as such a
+// mask combines with others on the scalar unit, and a ballot of it costs no
+// vector instructions (a ballot of a combined bool is rebuilt lane by lane).
+__device__ __forceinline__ bool lane_bit(unsigned long long mask) { return __builtin_amdgcn_inverse_ballot_w64(mask); }
 
 template <typename T> __device__ __forceinline__ T inf_of();
 template <> __device__ __forceinline__ double inf_of<double>() { return __builtin_huge_val(); }
