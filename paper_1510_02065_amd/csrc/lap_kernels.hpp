@@ -86,17 +86,47 @@ __device__ __forceinline__ long long xcd_major(long long b, long long grid)
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// Stage one problem per segment and solve it (the residual written over the
+// block when blk is not null); S to every lane.  Called twice by the kernel
+// below: with the size as a scalar (readfirstlane) when every problem of the
+// wave has it, as in every wave of one instance's family, so that loop
+// counts, clamps, bit masks and LDS offsets that depend only on n run on the
+// scalar unit, and with the per-lane size otherwise (a wave across an
+// instance boundary, or with segments past the last problem, whose n is 0).
+// Both compute the same values.
+template <typename T, int SEG, int K, bool AUC, bool DOWN>
+__device__ __forceinline__ double stage_and_solve(unsigned char* smem, int seg, int lane, int nmax, int n, T* blk,
+                                                  long long ld)
+{
+    const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
+    stage_block<T, SEG, K>(sc.M, sc.ld, blk, ld, n, lane);
+    wave_sync();
+    static_assert(!AUC || K == 1, "the auction solver takes one column per lane");
+    if constexpr (AUC)
+        return lap_auction_flat<T, SEG, DOWN>(sc, n, blk, ld, nullptr, nullptr);
+    else if constexpr (K == 1)
+        return lap_concentrate_flat<T, SEG, DOWN>(sc, n, blk, ld, nullptr, nullptr);
+    else if constexpr (SEG >= 16)
+        return lap_concentrate_flatk<T, SEG, K, DOWN>(sc, n, blk, ld, nullptr, nullptr);
+    else
+        return lap_concentrate_slots<T, SEG, K, DOWN>(sc, n, blk, ld, nullptr, nullptr);
+}
+
 // D -> C (FAM kFamD: blocks D_beta of size N-2, parent c_beta) or C -> B
 // (kFamC: blocks C_ij of size N-1, parent b_ij), K columns per lane, 64/SEG
 // problems per wave, one wave per workgroup.  parent += S, the block is
 // replaced by its residual, values[...] = S when values is not null (values
 // are packed like the parents).  `mode` applies to the D family only.  AUC:
-// the auction solver (one column per lane only).
+// the auction solver (one column per lane only).  Registers: with one
+// column per lane the FP32 kernels are held to 72 VGPRs (seven waves per
+// SIMD, about what their LDS allows at n = 23) and the FP64 ones of up to 32
+// lanes to 80 (six waves: the LDS of the smaller problems of a batch allows
+// more than the 99 VGPRs they would otherwise take); neither spills.
 template <int PM, int SEG, int K, int FAM, bool AUC = false>
-__global__ __launch_bounds__(64) void k_lap_family_s(StoreT<PM>* __restrict__ D, StoreT<PM>* __restrict__ C,
-                                                     StoreT<PM>* __restrict__ B, const Inst* __restrict__ inst,
-                                                     FamilyClass fc, int nmax, double* __restrict__ values, int mode,
-                                                     const int* __restrict__ act)
+__global__ __launch_bounds__(64, K > 1 ? 1 : (PM != kPrecF64 ? 7 : (SEG <= 32 ? 6 : 1)))
+void k_lap_family_s(StoreT<PM>* __restrict__ D, StoreT<PM>* __restrict__ C, StoreT<PM>* __restrict__ B,
+                    const Inst* __restrict__ inst, FamilyClass fc, int nmax, double* __restrict__ values, int mode,
+                    const int* __restrict__ act)
 {
     using T = StoreT<PM>;
     constexpr bool DOWN = PM == kPrecF32Down;
@@ -136,19 +166,11 @@ __global__ __launch_bounds__(64) void k_lap_family_s(StoreT<PM>* __restrict__ D,
             pidx = I.offB + b;
         }
     }
-    const SlotScratch<T, SEG, K> sc(smem + seg * SlotLds<T, SEG, K>::bytes(nmax), n);
-    stage_block<T, SEG, K>(sc.M, sc.ld, blk, ld, n, lane);
-    wave_sync();
-    double S;
-    static_assert(!AUC || K == 1, "the auction solver takes one column per lane");
-    if constexpr (AUC)
-        S = lap_auction_flat<T, SEG, DOWN>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
-    else if constexpr (K == 1)
-        S = lap_concentrate_flat<T, SEG, DOWN>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
-    else if constexpr (SEG >= 16)
-        S = lap_concentrate_flatk<T, SEG, K, DOWN>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
-    else
-        S = lap_concentrate_slots<T, SEG, K, DOWN>(sc, n, active ? blk : nullptr, ld, nullptr, nullptr);
+    const int nu = __builtin_amdgcn_readfirstlane(n);
+    T* const bw = active ? blk : nullptr;
+    const double S = ballot64(n != nu) == 0
+                         ? stage_and_solve<T, SEG, K, AUC, DOWN>(smem, seg, lane, nmax, nu, bw, ld)
+                         : stage_and_solve<T, SEG, K, AUC, DOWN>(smem, seg, lane, nmax, n, bw, ld);
     if (active && lane == 0) {
         T* parent = (FAM == kFamD) ? C : B;
         parent[pidx] = store_add<PM>(parent[pidx], S);
@@ -247,19 +269,24 @@ __global__ __launch_bounds__(64) void k_lap_batch(int count, const int* __restri
     int n = in ? nv[b] : 0;
     const bool bad = n < 0 || n > SEG;
     if (bad) n = 0;
-    const SlotScratch<T, SEG, 1> sc(smem + seg * SlotLds<T, SEG, 1>::bytes(SEG), n);
     T* mat = (in && !bad) ? cost + mat_off[b] : nullptr;
     const int64_t vo = (in && !bad && vec_off) ? vec_off[b] : 0;
-    stage_block<T, SEG, 1>(sc.M, sc.ld, mat, n, n, lane);
-    wave_sync();
     T* const Rw = (write_residual && n > 0) ? mat : nullptr;
     T* const dw = (duals && n > 0) ? duals + 4 * vo : nullptr;
     int32_t* const aw = (assign && n > 0) ? assign + vo : nullptr;
-    double S;
-    if constexpr (AUC)
-        S = lap_auction_flat<T, SEG, PM == kPrecF32Down>(sc, n, Rw, n, dw, aw);
-    else
-        S = lap_concentrate_flat<T, SEG, PM == kPrecF32Down>(sc, n, Rw, n, dw, aw);
+    // The size as a scalar when every problem of the wave has it, as in
+    // k_lap_family_s.
+    auto solve = [&](int nn) __attribute__((always_inline)) -> double {
+        const SlotScratch<T, SEG, 1> sc(smem + seg * SlotLds<T, SEG, 1>::bytes(SEG), nn);
+        stage_block<T, SEG, 1>(sc.M, sc.ld, mat, nn, nn, lane);
+        wave_sync();
+        if constexpr (AUC)
+            return lap_auction_flat<T, SEG, PM == kPrecF32Down>(sc, nn, Rw, nn, dw, aw);
+        else
+            return lap_concentrate_flat<T, SEG, PM == kPrecF32Down>(sc, nn, Rw, nn, dw, aw);
+    };
+    const int nu = __builtin_amdgcn_readfirstlane(n);
+    const double S = ballot64(n != nu) == 0 ? solve(nu) : solve(n);
     // A quiet NaN written by bit pattern marks a problem that was not solved.
     if (in && lane == 0) value[b] = bad ? __longlong_as_double(0x7ff8000000000000ll) : S;
 }

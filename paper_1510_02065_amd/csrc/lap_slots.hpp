@@ -481,9 +481,11 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
                                                                const int (&c)[K], const bool (&ok)[K], T (&v)[K],
                                                                int (&row)[K])
 {
-    // Each loop reads kReduceChunk LDS entries before it uses any of them
-    // (indices past n - 1 re-read entry n - 1, which changes no minimum and
-    // sets no new bit), so a lane waits for LDS once per chunk.  Zero masks are
+    // Each loop reads kReduceChunk LDS entries before it uses any of them, so
+    // a lane waits for LDS once per chunk; whole chunks first, whose offsets
+    // are the chunk's base plus constants, then the last partial one (indices
+    // past n - 1 re-read entry n - 1, which changes no minimum and sets no new
+    // bit).  Zero masks are
     // 32-bit when a problem has at most 32 columns.  The minima are fmin (one
     // instruction in FP64 where a select takes three; equal values can differ
     // only in the sign of a zero, which no later comparison or sum sees), the
@@ -497,7 +499,15 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
         if (!ok[s]) continue;
         const T* __restrict__ Mr = M + __umul24(c[s], ldm);
         T um = Mr[0];
-        for (int q0 = 0; q0 < n; q0 += kReduceChunk) {
+        int q0 = 0;
+        for (; q0 + kReduceChunk <= n; q0 += kReduceChunk) {
+            T m[kReduceChunk];
+#pragma unroll
+            for (int e = 0; e < kReduceChunk; ++e) m[e] = Mr[q0 + e];
+#pragma unroll
+            for (int e = 0; e < kReduceChunk; ++e) um = tmin(m[e], um);
+        }
+        if (q0 < n) {
             T m[kReduceChunk];
 #pragma unroll
             for (int e = 0; e < kReduceChunk; ++e) m[e] = Mr[min(q0 + e, n - 1)];
@@ -516,7 +526,22 @@ __device__ __forceinline__ unsigned long long lap_reduce_start(const SlotScratch
         const T* __restrict__ Mc = M + c[s];
         T vm = Mc[0] - sc.vt[0];
         Mask z = 1;
-        for (int r0 = 0; r0 < n; r0 += kReduceChunk) {
+        int r0 = 0;
+        for (; r0 + kReduceChunk <= n; r0 += kReduceChunk) {
+            const T* __restrict__ Mc0 = Mc + __umul24(r0, ldm);
+            const T* __restrict__ u0 = sc.vt + r0;
+            T x[kReduceChunk];
+#pragma unroll
+            for (int e = 0; e < kReduceChunk; ++e) x[e] = Mc0[e * ldm] - u0[e];
+#pragma unroll
+            for (int e = 0; e < kReduceChunk; ++e) {
+                const Mask bit = Mask(1) << (r0 + e);
+                const bool lt = x[e] < vm, eq = x[e] == vm;
+                z = lt ? bit : (eq ? (z | bit) : z);
+                vm = tmin(x[e], vm);
+            }
+        }
+        if (r0 < n) {
             T x[kReduceChunk];
 #pragma unroll
             for (int e = 0; e < kReduceChunk; ++e) {
