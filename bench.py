@@ -40,16 +40,16 @@ HBM_PEAK_GBS = 8000.0
 # until the counters are taken again.
 TRAFFIC = {
     # (step, N, precision, complementary pairs once): (csrc digest, scaled FETCH bytes, scaled WRITE bytes)
-    (4, 25, "fp64", True): ("dafd76a3bc7dc3e0", 373937.8 * 1024 * 2.0, 780508.6 * 1024 * 1.0),
-    (3, 25, "fp64", True): ("dafd76a3bc7dc3e0", 397679.7 * 1024 * 2.0, 743988.6 * 1024 * 1.0),
-    (4, 25, "fp32", True): ("dafd76a3bc7dc3e0", 187175.5 * 1024 * 2.0, 389221.6 * 1024 * 1.0),
-    (3, 25, "fp32", True): ("dafd76a3bc7dc3e0", 211211.6 * 1024 * 2.0, 390444.1 * 1024 * 1.0),
-    (4, 25, "fp32n", True): ("dafd76a3bc7dc3e0", 187163.4 * 1024 * 2.0, 389820.0 * 1024 * 1.0),
-    (3, 25, "fp32n", True): ("dafd76a3bc7dc3e0", 201867.7 * 1024 * 2.0, 372029.8 * 1024 * 1.0),
-    (4, 40, "fp64", True): ("dafd76a3bc7dc3e0", 6878438.7 * 1024 * 2.0, 14736141.8 * 1024 * 1.0),
-    (3, 40, "fp64", True): ("dafd76a3bc7dc3e0", 7964880.7 * 1024 * 2.0, 17096457.9 * 1024 * 1.0),
-    (4, 40, "fp32", True): ("dafd76a3bc7dc3e0", 3441700.2 * 1024 * 2.0, 8011717.5 * 1024 * 1.0),
-    (3, 40, "fp32", True): ("dafd76a3bc7dc3e0", 3716138.2 * 1024 * 2.0, 13733763.1 * 1024 * 1.0),
+    (4, 25, "fp64", True): ("48ce863f5d0130d8", 373952.4 * 1024 * 2.0, 774286.3 * 1024 * 1.0),
+    (3, 25, "fp64", True): ("48ce863f5d0130d8", 397714.9 * 1024 * 2.0, 743996.1 * 1024 * 1.0),
+    (4, 25, "fp32", True): ("48ce863f5d0130d8", 187197.0 * 1024 * 2.0, 385420.4 * 1024 * 1.0),
+    (3, 25, "fp32", True): ("48ce863f5d0130d8", 211227.3 * 1024 * 2.0, 390437.3 * 1024 * 1.0),
+    (4, 25, "fp32n", True): ("48ce863f5d0130d8", 187172.3 * 1024 * 2.0, 386180.9 * 1024 * 1.0),
+    (3, 25, "fp32n", True): ("48ce863f5d0130d8", 201844.8 * 1024 * 2.0, 372027.2 * 1024 * 1.0),
+    (4, 40, "fp64", True): ("48ce863f5d0130d8", 6877959.3 * 1024 * 2.0, 14611774.7 * 1024 * 1.0),
+    (3, 40, "fp64", True): ("48ce863f5d0130d8", 7947267.8 * 1024 * 2.0, 17150922.9 * 1024 * 1.0),
+    (4, 40, "fp32", True): ("48ce863f5d0130d8", 3441542.8 * 1024 * 2.0, 7922078.5 * 1024 * 1.0),
+    (3, 40, "fp32", True): ("48ce863f5d0130d8", 3716187.3 * 1024 * 2.0, 13650580.4 * 1024 * 1.0),
 }
 
 
