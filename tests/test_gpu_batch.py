@@ -1,7 +1,10 @@
 """Many instances in one handle: branch-and-bound nodes of different sizes.
 
 * a batch handle gives bit for bit the same trajectory and state as one handle
-  per instance (the kernels treat each instance identically);
+  per instance (the kernels treat each instance identically; an assignment
+  wave that spans two nodes of different sizes runs the solver with per-lane
+  sizes, a single instance's waves with a scalar size, so these tests also
+  pin the two code paths to each other);
 * every node's trajectory matches the FP64 oracle run on that node;
 * node bound + node constant never exceeds the brute-force optimum of the
   completion problem;
